@@ -1,0 +1,100 @@
+"""The three search stages and the full pipeline (section 4.1).
+
+1. GPU piloting: Algorithm 1 on the sampled subgraph with reduced vectors,
+   started from the entries that fast entry selection returns.
+2. Residual refinement: complete distances for the stage-1 candidates (primary
+   plus residual part, which in exact arithmetic is the full distance and is
+   computed here directly on the full vectors), a re-ranking, then two loop
+   steps of Algorithm 1 on the subgraph with full distances; the outputs are
+   the re-ranked candidates and the visited set.
+3. Final traversal: Algorithm 1 on the full graph with full vectors, starting
+   from the stage-2 candidates (all unchecked again, because the full graph's
+   edges differ) with the stage-2 visited set pre-populated.
+
+Only the candidate list crosses from stage 1 to stage 2 (section 4.1 summary:
+the query goes to the GPU, a small candidate set comes back), so stage 2
+starts with the handed-off ids as its visited set.  With stage 1 switched off
+the pipeline is plain Algorithm 1 from the entries (graceful degradation,
+section 4.1 summary).  The effective final list size is max(ef, k) because
+k <= ef (section 2.2).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .entries import select_entries
+from .metric import delta_many
+from .projection import project
+from .traverse import greedy_search
+
+
+def gpu_stage(qr, Xr, sub_rowptr, sub_nbrs, entries, ef: int, metric: str = "l2"):
+    """Stage 1 for one reduced query: Algorithm 1 on the subgraph."""
+    return greedy_search(qr, Xr, sub_rowptr, sub_nbrs, ef, entries, metric)
+
+
+def refine(q, X, sub_rowptr, sub_nbrs, beam_ids, ef_cpu: int, metric: str = "l2", steps: int = 2):
+    """Stage 2 for one query; returns the Algorithm 1 result dict plus total n_dist."""
+    ids = [int(v) for v in beam_ids if v >= 0]
+    d = delta_many(q, X[np.asarray(ids, dtype=np.int64)], metric) if ids else np.zeros(0)
+    res = greedy_search(q, X, sub_rowptr, sub_nbrs, ef_cpu, (), metric,
+                        initial=list(zip(d.tolist(), ids)), max_steps=steps)
+    res["n_dist"] += len(ids)
+    return res
+
+
+def final_traversal(q, X, rowptr, nbrs, cand_ids, cand_dists, visited, ef_cpu: int, k: int,
+                    metric: str = "l2"):
+    """Stage 3 for one query; returns (ids [k], dists [k], result dict), padded with (-1, inf)."""
+    ef = max(ef_cpu, k)
+    res = greedy_search(q, X, rowptr, nbrs, ef, (), metric,
+                        initial=list(zip(np.asarray(cand_dists).tolist(), np.asarray(cand_ids).tolist())),
+                        visited=visited)
+    ids = np.full(k, -1, dtype=np.int64)
+    dists = np.full(k, np.inf)
+    take = min(k, res["ids"].size)
+    ids[:take] = res["ids"][:take]
+    dists[:take] = res["dists"][:take]
+    return ids, dists, res
+
+
+def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets, pivot_vecs,
+             pivot_ids, *, k: int, ef_gpu: int, ef_cpu: int, E: int, metric: str = "l2",
+             refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True):
+    """All stages for every query; returns (ids [m][k], dists [m][k], counters [m][4]).
+
+    counters = (stage-1 distances, stage-2 distances, stage-3 distances, stage-3 steps).
+    """
+    Q = np.asarray(Q, dtype=np.float64)
+    Qr = project(Q, V)
+    entries, _, _, _ = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
+    m = Q.shape[0]
+    out_i = np.full((m, k), -1, dtype=np.int64)
+    out_d = np.full((m, k), np.inf)
+    counters = np.zeros((m, 4), dtype=np.int64)
+    for i in range(m):
+        if use_gpu_stage:
+            g = gpu_stage(Qr[i], Xr, sub_rowptr, sub_nbrs, entries[i], ef_gpu, metric)
+            counters[i, 0] = g["n_dist"]
+            if use_refine:
+                r = refine(Q[i], X, sub_rowptr, sub_nbrs, g["ids"], ef_cpu, metric, refine_steps)
+                counters[i, 1] = r["n_dist"]
+                c_ids, c_d, vis = r["ids"], r["dists"], r["visited"]
+            else:
+                c_ids = g["ids"]
+                c_d = delta_many(Q[i], X[c_ids], metric) if c_ids.size else np.zeros(0)
+                counters[i, 1] = c_ids.size
+                vis = set(int(v) for v in c_ids)
+            ids, d, f = final_traversal(Q[i], X, rowptr, nbrs, c_ids, c_d, vis, ef_cpu, k, metric)
+        else:
+            ef = max(ef_cpu, k)
+            f = greedy_search(Q[i], X, rowptr, nbrs, ef, entries[i], metric)
+            ids = np.full(k, -1, dtype=np.int64)
+            d = np.full(k, np.inf)
+            t = min(k, f["ids"].size)
+            ids[:t], d[:t] = f["ids"][:t], f["dists"][:t]
+        counters[i, 2] = f["n_dist"]
+        counters[i, 3] = f["n_exp"]
+        out_i[i], out_d[i] = ids, d
+    return out_i, out_d, counters

@@ -1,0 +1,112 @@
+"""Greedy best-first search, Algorithm 1 ("ANNS by Greedy Search"), section 2.2.
+
+The candidate list C holds (distance, id, checked) entries.  Each loop step
+takes the first unchecked entry u, marks it checked, computes the distance of
+every not-yet-visited out-neighbour of u (marking it visited), inserts it, and
+finally resizes C to ef.  The search ends when C holds no unchecked entry.
+
+Readings where the paper is silent:
+* order: C is ordered by the key (distance, id), a strict total order;
+* entry points: each entry is marked visited and scored once when C is
+  initialised (entries already visited, or equal to -1, are skipped), and the
+  initial C is resized to ef (the first expansion is the same either way);
+* visited is an exact set, one distance per visited node, so
+  n_dist = |visited| (the paper's lossy GPU filter is a separate variant);
+* expansion width is one node per loop step, as printed.
+
+Inputs for the later stages: ``initial`` seeds C with already scored
+(distance, id) pairs, ``visited`` pre-populates the visited set and
+``max_steps`` bounds the number of loop steps (the refinement stage runs two).
+
+The returned ``margin`` is the smallest relative gap between neighbouring keys
+among the first ef+1 positions of C over all steps: when it is tiny, a
+different rounding of the distances may legitimately change the path.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from .metric import delta_many
+
+
+def _gap(sorted_keys, ef: int) -> float:
+    head = [d for d, _ in sorted_keys[:ef + 1]]
+    best = np.inf
+    for a, b in zip(head, head[1:]):
+        scale = max(abs(a), abs(b), 1e-300)
+        best = min(best, (b - a) / scale)
+    return best
+
+
+def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "l2", *,
+                  initial=None, visited=None, max_steps=None):
+    """Run Algorithm 1 for one query.
+
+    q        query vector (any float dtype; used in fp64)
+    vectors  base vectors indexed by node id
+    rowptr, nbrs   CSR out-neighbours in stored order
+    Returns a dict with ``ids``/``dists`` (C in key order, at most ef),
+    ``checked`` flags, ``n_exp`` (loop steps), ``n_dist`` (distances computed
+    here), ``visited`` (the final set) and ``margin``.
+    """
+    if ef < 1:
+        raise ValueError("ef must be >= 1")
+    q = np.asarray(q, dtype=np.float64)
+    seen = set() if visited is None else set(int(v) for v in visited)
+    n_dist = 0
+    # line 3: C <- EP
+    C = []  # list of [key=(distance, id), checked]
+    if initial is not None:
+        for d, v in initial:
+            C.append([(float(d), int(v)), False])
+            seen.add(int(v))
+    fresh = []
+    for e in entries:
+        e = int(e)
+        if e < 0 or e in seen:
+            continue
+        seen.add(e)
+        fresh.append(e)
+    if fresh:
+        ds = delta_many(q, vectors[np.asarray(fresh)], metric)
+        n_dist += len(fresh)
+        for d, v in zip(ds, fresh):
+            C.append([(float(d), v), False])
+    C.sort(key=lambda c: c[0])
+    margin = _gap([c[0] for c in C], ef)
+    del C[ef:]
+    n_exp = 0
+    while max_steps is None or n_exp < max_steps:
+        # line 5: the first unchecked node in C
+        pos = next((i for i, c in enumerate(C) if not c[1]), None)
+        if pos is None:
+            break  # line 12: no unchecked node left
+        C[pos][1] = True
+        u = C[pos][0][1]
+        n_exp += 1
+        # lines 6-10: unvisited out-neighbours, mark, score, insert
+        new = []
+        for v in nbrs[rowptr[u]:rowptr[u + 1]]:
+            v = int(v)
+            if v not in seen:
+                seen.add(v)
+                new.append(v)
+        if new:
+            ds = delta_many(q, vectors[np.asarray(new)], metric)
+            n_dist += len(new)
+            for d, v in zip(ds, new):
+                C.append([(float(d), v), False])
+            C.sort(key=lambda c: c[0])
+            margin = min(margin, _gap([c[0] for c in C], ef))
+        # line 11: C.resize(ef)
+        del C[ef:]
+    return {
+        "ids": np.asarray([c[0][1] for c in C], dtype=np.int64),
+        "dists": np.asarray([c[0][0] for c in C], dtype=np.float64),
+        "checked": np.asarray([c[1] for c in C], dtype=bool),
+        "n_exp": n_exp,
+        "n_dist": n_dist,
+        "visited": seen,
+        "margin": margin,
+    }

@@ -1,0 +1,202 @@
+"""Seeded base/query vectors and the random draws the method consumes.
+
+Generator recipe (the same on every machine, independent of memory size):
+
+* every stream is ``numpy.random.Generator(PCG64(SeedSequence([seed, *keys])))``;
+* base/query rows are produced in fixed chunks of ``CHUNK`` rows, chunk ``c``
+  drawing from its own stream ``[seed, c]`` so any row range can be
+  regenerated without producing the rows before it;
+* ``seed = 1000 * config + offset`` with offsets +0 base vectors, +1 queries,
+  +3 node order for sampling, +4 pivots and k-means seeds, +5 arrivals,
+  +6 spectral basis.
+
+Gaussian mixtures (the 96/128-dim workloads): ``K`` equally likely components,
+centres ~ N(0, 4 I), points = centre + N(0, I).  Anisotropic mixtures (the
+768-dim inner-product workloads): a seeded orthonormal basis ``B`` (QR of a
+Gaussian matrix, signs fixed so diag(R) > 0) and a power-law spectrum
+``lambda_i = 1 / i``; centres ``2 B diag(sqrt(lambda)) z``, points
+``centre + B diag(sqrt(lambda)) eps``, then every point scaled to unit length.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+CHUNK = 1_000_000
+
+OFF_BASE, OFF_QUERY, OFF_ORDER, OFF_PIVOT, OFF_ARRIVAL, OFF_BASIS = 0, 1, 3, 4, 5, 6
+
+
+@dataclass(frozen=True)
+class WorkloadSpec:
+    """Shape and parameters of one synthetic workload."""
+
+    name: str
+    config: int
+    n: int
+    dim: int
+    components: int
+    queries: int
+    metric: str  # "l2" | "ip"
+    k: int
+    degree: int
+    d_r: int
+    rho: float
+    sample_mode: str  # "uniform" | "seed_expand"
+    n_pivots: int
+    ef: tuple
+    kind: str = "gmm"  # "gmm" | "aniso"
+    r: int = 32
+    xr_dtypes: tuple = ("f32",)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def seed(self) -> int:
+        return 1000 * self.config
+
+
+SPECS = {
+    "tiny": WorkloadSpec(
+        name="tiny", config=1, n=10_000, dim=96, components=64, queries=1_000,
+        metric="l2", k=10, degree=32, d_r=32, rho=0.25, sample_mode="uniform",
+        n_pivots=256, ef=(64,), xr_dtypes=("f32",)),
+    "gmm1m": WorkloadSpec(
+        name="gmm1m", config=2, n=1_000_000, dim=128, components=1024,
+        queries=10_000, metric="l2", k=10, degree=32, d_r=64, rho=0.25,
+        sample_mode="seed_expand", n_pivots=4096,
+        ef=(32, 48, 64, 96, 128, 192, 256, 384, 512), xr_dtypes=("f32", "f16")),
+    "aniso10m": WorkloadSpec(
+        name="aniso10m", config=3, n=10_000_000, dim=768, components=1024,
+        queries=10_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
+        sample_mode="seed_expand", n_pivots=65_536, ef=(64, 128, 256, 512),
+        kind="aniso", xr_dtypes=("bf16",)),
+    "gmm100m": WorkloadSpec(
+        name="gmm100m", config=4, n=100_000_000, dim=96, components=16_384,
+        queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
+        sample_mode="seed_expand", n_pivots=16_384, ef=(64, 128, 256, 512),
+        xr_dtypes=("f16",)),
+    "serve20m": WorkloadSpec(
+        name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
+        queries=100_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
+        sample_mode="seed_expand", n_pivots=65_536, ef=(64, 128, 256, 512),
+        kind="aniso", xr_dtypes=("f16",)),
+}
+
+
+def make_rng(seed: int, *keys: int) -> np.random.Generator:
+    """Independent PCG64 stream for (seed, keys...)."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), *map(int, keys)])))
+
+
+def gmm_centers(seed: int, components: int, dim: int) -> np.ndarray:
+    """Mixture centres ~ N(0, 4 I) as float64 [components][dim]."""
+    rng = make_rng(seed, 0x7FFF_FFFF)
+    return 2.0 * rng.standard_normal((components, dim))
+
+
+def _basis(seed: int, dim: int) -> np.ndarray:
+    rng = make_rng(seed + OFF_BASIS, 0)
+    g = rng.standard_normal((dim, dim))
+    q, r = np.linalg.qr(g)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return q * s[None, :]
+
+
+def _aniso_model(seed: int, components: int, dim: int):
+    b = _basis(seed, dim)
+    lam = 1.0 / np.arange(1, dim + 1, dtype=np.float64)
+    scale = b * np.sqrt(lam)[None, :]  # B diag(sqrt(lambda))
+    rng = make_rng(seed, 0x7FFF_FFFE)
+    z = rng.standard_normal((components, dim))
+    centres = 2.0 * z @ scale.T
+    return centres, scale
+
+
+def _chunk_rows(seed: int, stream_seed: int, chunk: int, n_rows: int, components: int,
+                dim: int, kind: str, model) -> np.ndarray:
+    rng = make_rng(stream_seed, chunk)
+    comp = rng.integers(0, components, size=n_rows)
+    eps = rng.standard_normal((n_rows, dim))
+    if kind == "gmm":
+        x = model[comp] + eps
+    else:
+        centres, scale = model
+        x = centres[comp] + eps @ scale.T
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return x.astype(np.float32)
+
+
+def _rows(spec: WorkloadSpec, stream_seed: int, total: int, start: int, stop: int) -> np.ndarray:
+    if spec.kind == "gmm":
+        model = gmm_centers(spec.seed, spec.components, spec.dim)
+    else:
+        model = _aniso_model(spec.seed, spec.components, spec.dim)
+    start, stop = max(0, start), min(total, stop)
+    out = np.empty((max(0, stop - start), spec.dim), dtype=np.float32)
+    c0, c1 = start // CHUNK, (stop - 1) // CHUNK if stop > start else -1
+    for c in range(c0, c1 + 1):
+        lo, hi = c * CHUNK, min(total, (c + 1) * CHUNK)
+        block = _chunk_rows(spec.seed, stream_seed, c, hi - lo, spec.components, spec.dim,
+                            spec.kind, model)
+        a, b = max(lo, start), min(hi, stop)
+        out[a - start:b - start] = block[a - lo:b - lo]
+    return out
+
+
+def gmm_points(seed: int, n: int, dim: int, components: int, stream_offset: int = OFF_BASE) -> np.ndarray:
+    """Gaussian-mixture rows without a WorkloadSpec (used by small tests)."""
+    spec = WorkloadSpec(name="adhoc", config=0, n=n, dim=dim, components=components, queries=0,
+                        metric="l2", k=10, degree=32, d_r=dim, rho=1.0, sample_mode="uniform",
+                        n_pivots=32, ef=(16,))
+    model = gmm_centers(seed, components, dim)
+    out = np.empty((n, dim), dtype=np.float32)
+    for c in range((n + CHUNK - 1) // CHUNK):
+        lo, hi = c * CHUNK, min(n, (c + 1) * CHUNK)
+        out[lo:hi] = _chunk_rows(seed, seed + stream_offset, c, hi - lo, components, dim, "gmm", model)
+    del spec
+    return out
+
+
+def anisotropic_points(seed: int, n: int, dim: int, components: int,
+                       stream_offset: int = OFF_BASE) -> np.ndarray:
+    """Unit-norm anisotropic-mixture rows without a WorkloadSpec."""
+    model = _aniso_model(seed, components, dim)
+    out = np.empty((n, dim), dtype=np.float32)
+    for c in range((n + CHUNK - 1) // CHUNK):
+        lo, hi = c * CHUNK, min(n, (c + 1) * CHUNK)
+        out[lo:hi] = _chunk_rows(seed, seed + stream_offset, c, hi - lo, components, dim, "aniso", model)
+    return out
+
+
+def base_vectors(spec: WorkloadSpec, start: int = 0, stop: int | None = None) -> np.ndarray:
+    """Rows [start, stop) of the base set, float32 [rows][dim]."""
+    stop = spec.n if stop is None else stop
+    return _rows(spec, spec.seed + OFF_BASE, spec.n, start, stop)
+
+
+def query_vectors(spec: WorkloadSpec, count: int | None = None) -> np.ndarray:
+    """The first ``count`` queries (same mixture, independent draws)."""
+    count = spec.queries if count is None else count
+    return _rows(spec, spec.seed + OFF_QUERY, max(count, 1), 0, count)
+
+
+def node_order(n: int, seed: int) -> np.ndarray:
+    """Seeded permutation of [0, n) consumed by node sampling (int64)."""
+    return make_rng(seed + OFF_ORDER, 0).permutation(n).astype(np.int64)
+
+
+def pivot_choice(candidates: np.ndarray, n_pivots: int, seed: int) -> np.ndarray:
+    """``n_pivots`` distinct node ids drawn uniformly from ``candidates`` (int32)."""
+    cand = np.sort(np.asarray(candidates, dtype=np.int64))
+    if n_pivots > cand.size:
+        raise ValueError("more pivots than candidate nodes")
+    idx = make_rng(seed + OFF_PIVOT, 0).choice(cand.size, size=n_pivots, replace=False)
+    return cand[idx].astype(np.int32)
+
+
+def kmeans_init_choice(n_pivots: int, r: int, seed: int) -> np.ndarray:
+    """``r`` distinct pivot positions that seed the coarse clustering (int32)."""
+    return make_rng(seed + OFF_PIVOT, 1).choice(n_pivots, size=r, replace=False).astype(np.int32)

@@ -1,0 +1,222 @@
+"""Proximity-graph fixtures standing in for the externally trained graph index.
+
+Recipe (the paper reuses a FAISS-built HNSW base layer; FAISS is not available
+here, so a graph of the same kind is built from scratch):
+
+1. exact ``cand``-NN of every node (fp64 order, ties by id);
+2. neighbour-selection heuristic of HNSW (relative-neighbourhood pruning): scan
+   candidates nearest first, drop ``c`` if an already kept ``s`` is closer to
+   ``c`` than the node itself, stop at ``R`` kept;
+3. reverse edges are added, each node's union of forward and (nearest ``R``)
+   reverse candidates is pruned again with the same rule when it exceeds ``R``;
+4. connectivity repair: nodes not reachable from the medoid are hung off the
+   nearest reachable node that still has a free slot (and linked back when the
+   new node has room), so every node is reachable from the medoid.
+
+Node sampling and the subgraph's reconnection use the same builder on the
+sampled rows only; the result is stored over all N rows with unsampled rows
+empty.  Rows are sorted by (distance, id).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import breadth_first_order, connected_components
+
+from .knn import exact_knn, pick_device
+
+
+def _pair_dist64(vecs: torch.Tensor) -> torch.Tensor:
+    """Squared L2 between all candidate pairs, [b][c][c] fp64."""
+    nrm = (vecs ** 2).sum(-1)
+    g = torch.bmm(vecs, vecs.transpose(1, 2).contiguous())
+    return (nrm[:, :, None] + nrm[:, None, :] - 2.0 * g).clamp(min=0.0)
+
+
+@torch.no_grad()
+def rng_prune(x64: torch.Tensor, cand: torch.Tensor, cdist: torch.Tensor, R: int,
+              keep_all_if_fits: bool = False, chunk: int = 8192) -> torch.Tensor:
+    """HNSW-style selection over sorted candidate rows; returns kept ids [n][R] (-1 pad)."""
+    n, c = cand.shape
+    out = torch.full((n, R), -1, dtype=torch.int64, device=cand.device)
+    for a in range(0, n, chunk):
+        ci = cand[a:a + chunk]
+        cd = cdist[a:a + chunk]
+        b = ci.shape[0]
+        valid = ci >= 0
+        if keep_all_if_fits:
+            cnt = valid.sum(1)
+        vecs = x64[ci.clamp(min=0)]
+        P = _pair_dist64(vecs)
+        keep = torch.zeros((b, c), dtype=torch.bool, device=ci.device)
+        count = torch.zeros(b, dtype=torch.int64, device=ci.device)
+        for i in range(c):
+            blocked = ((P[:, i, :] < cd[:, i:i + 1]) & keep).any(1)
+            take = valid[:, i] & ~blocked & (count < R)
+            if keep_all_if_fits:
+                take = take | (valid[:, i] & (cnt <= R))
+            keep[:, i] = take
+            count += take.long()
+        # compact kept ids preserving order
+        pos = torch.cumsum(keep.long(), 1) - 1
+        rows = torch.arange(b, device=ci.device)[:, None].expand(b, c)
+        sel = keep & (pos < R)
+        blk = torch.full((b, R), -1, dtype=torch.int64, device=ci.device)
+        blk[rows[sel], pos[sel]] = ci[sel]
+        out[a:a + b] = blk
+    return out
+
+
+@torch.no_grad()
+def _add_reverse(x64: torch.Tensor, fwd: torch.Tensor, R: int) -> torch.Tensor:
+    """Union of forward rows and nearest-R reverse candidates, re-pruned to R."""
+    dev = fwd.device
+    n = fwd.shape[0]
+    src = torch.arange(n, device=dev)[:, None].expand_as(fwd)
+    m = fwd >= 0
+    s, d = src[m], fwd[m]
+    # forward (s -> d) and reverse (d -> s) proposals
+    node = torch.cat([s, d])
+    nbr = torch.cat([d, s])
+    key = torch.unique(node * n + nbr)
+    node, nbr = key // n, key % n
+    dist = ((x64[node] - x64[nbr]) ** 2).sum(-1)
+    # group by node, ascending (dist, id)
+    o = torch.argsort(nbr, stable=True)
+    node, nbr, dist = node[o], nbr[o], dist[o]
+    o = torch.argsort(dist, stable=True)
+    node, nbr, dist = node[o], nbr[o], dist[o]
+    o = torch.argsort(node, stable=True)
+    node, nbr, dist = node[o], nbr[o], dist[o]
+    counts = torch.bincount(node, minlength=n)
+    starts = torch.cumsum(counts, 0) - counts
+    rank = torch.arange(node.shape[0], device=dev) - starts[node]
+    width = 2 * R
+    sel = rank < width
+    cand = torch.full((n, width), -1, dtype=torch.int64, device=dev)
+    cd = torch.full((n, width), float("inf"), dtype=torch.float64, device=dev)
+    cand[node[sel], rank[sel]] = nbr[sel]
+    cd[node[sel], rank[sel]] = dist[sel]
+    return rng_prune(x64, cand, cd, R, keep_all_if_fits=True)
+
+
+def _csr(adj: np.ndarray, n: int) -> csr_matrix:
+    rows = np.repeat(np.arange(n), adj.shape[1])
+    cols = adj.reshape(-1)
+    m = cols >= 0
+    return csr_matrix((np.ones(int(m.sum()), dtype=np.int8), (rows[m], cols[m])), shape=(n, n))
+
+
+def _reached_from(adj: np.ndarray, start: int) -> np.ndarray:
+    order = breadth_first_order(_csr(adj, adj.shape[0]), start, directed=True, return_predecessors=False)
+    r = np.zeros(adj.shape[0], dtype=bool)
+    r[order] = True
+    return r
+
+
+def _append(adj: np.ndarray, u: int, v: int) -> bool:
+    row = adj[u]
+    if (row == v).any():
+        return True
+    free = np.nonzero(row < 0)[0]
+    if free.size == 0:
+        return False
+    row[free[0]] = v
+    return True
+
+
+def _repair(X: np.ndarray, adj: np.ndarray, medoid: int, device) -> np.ndarray:
+    n, R = adj.shape
+    for _ in range(64):
+        reached = _reached_from(adj, medoid)
+        if reached.all():
+            return adj
+        # one representative per weakly connected piece of the unreached part
+        sub = np.nonzero(~reached)[0]
+        ncomp, lab = connected_components(_csr(adj, n), directed=True, connection="weak")
+        reps = []
+        seen = set()
+        for v in sub:
+            if lab[v] not in seen:
+                seen.add(lab[v])
+                reps.append(int(v))
+        if len(reps) == 0:
+            reps = [int(sub[0])]
+        host_ok = reached & (adj < 0).any(1)
+        if not host_ok.any():
+            host_ok = reached
+        near, _ = exact_knn(X, X[reps], 1, "l2", device=device, candidate_mask=host_ok)
+        for u, h in zip(reps, near[:, 0].tolist()):
+            if not _append(adj, int(h), u):
+                adj[int(h), -1] = u
+            _append(adj, u, int(h))
+    if not _reached_from(adj, medoid).all():
+        raise RuntimeError("connectivity repair did not converge")
+    return adj
+
+
+def medoid_of(X: np.ndarray) -> int:
+    mu = X.astype(np.float64).mean(0)
+    d = ((X.astype(np.float64) - mu) ** 2).sum(1)
+    return int(np.argmin(d))
+
+
+@torch.no_grad()
+def build_graph(X: np.ndarray, R: int, cand: int | None = None, *, device=None,
+                repair: bool = True) -> np.ndarray:
+    """Degree-<=R proximity graph over the rows of X as a padded [n][R] int32 array."""
+    dev = pick_device(device)
+    n = X.shape[0]
+    cand = R if cand is None else cand
+    cand = min(cand, n - 1)
+    ids, dist = exact_knn(X, None, cand, "l2", device=dev, exclude_self=True)
+    x64 = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32)).to(dev).double()
+    ci = torch.as_tensor(ids).to(dev)
+    cd = torch.as_tensor(dist).to(dev)
+    fwd = rng_prune(x64, ci, cd, R)
+    full = _add_reverse(x64, fwd, R)
+    adj = full.cpu().numpy()
+    # rows sorted by (distance, id)
+    adj = _sort_rows(X, adj)
+    if repair:
+        adj = _repair(X, adj, medoid_of(X), dev)
+        adj = _sort_rows(X, adj)
+    return adj.astype(np.int32)
+
+
+def _sort_rows(X: np.ndarray, adj: np.ndarray) -> np.ndarray:
+    x = X.astype(np.float64)
+    out = np.full_like(adj, -1)
+    step = 65536
+    for a in range(0, adj.shape[0], step):
+        blk = adj[a:a + step]
+        v = x[np.clip(blk, 0, None)]
+        d = ((v - x[a:a + step, None, :]) ** 2).sum(-1)
+        d = np.where(blk >= 0, d, np.inf)
+        key_id = np.where(blk >= 0, blk, np.iinfo(np.int64).max)
+        o = np.lexsort((key_id, d), axis=1)
+        out[a:a + step] = np.take_along_axis(blk, o, 1)
+    return out
+
+
+def padded_to_csr(adj: np.ndarray):
+    """[n][R] padded rows -> (rowptr int64 [n+1], nbrs int32)."""
+    deg = (adj >= 0).sum(1)
+    rowptr = np.zeros(adj.shape[0] + 1, dtype=np.int64)
+    np.cumsum(deg, out=rowptr[1:])
+    nbrs = adj[adj >= 0].astype(np.int32)
+    return rowptr, nbrs
+
+
+def build_subgraph_csr(X: np.ndarray, mask: np.ndarray, R: int, cand: int | None = None, *,
+                       device=None):
+    """Reconnect the sampled rows with the same builder; CSR over all N rows."""
+    sel = np.nonzero(mask)[0]
+    local = build_graph(X[sel], R, cand, device=device)
+    glob = np.where(local >= 0, sel[np.clip(local, 0, None)], -1)
+    n = X.shape[0]
+    full = np.full((n, R), -1, dtype=np.int64)
+    full[sel] = glob
+    return padded_to_csr(full)
