@@ -1,0 +1,320 @@
+/*
+ * pilotann.h - C ABI of the PilotANN GPU-stage library for AMD Instinct MI355X (gfx950).
+ *
+ * PilotANN (multi-stage graph ANNS) splits a top-k query into
+ *   stage 1  GPU piloting: greedy search (Algorithm 1) on a sampled subgraph with
+ *            SVD-reduced vectors, started from fast-entry-selection (FES) entries;
+ *   stage 2  residual refinement on the host: full distances of the GPU candidates,
+ *            re-rank, two traversal steps on the subgraph, a visited table;
+ *   stage 3  final traversal on the host: Algorithm 1 on the full graph with full
+ *            vectors from the stage-2 candidates and visited table.
+ * Section numbers below refer to the paper (4.1 multi-stage processing, 4.3
+ * methodology details, 5 fast entry selection, Algorithm 1, Algorithm 2, Table 2).
+ *
+ * Conventions shared by every call
+ *   - Every call returns a pa_status: PA_OK (0) or a negative code.  On failure
+ *     pa_last_error() returns a message for the calling thread; no C++ exception
+ *     crosses this boundary and outputs are left unspecified.
+ *   - "_dev" pointers are device (HBM) pointers on the current HIP device;
+ *     "_host" pointers are host pointers.  The library never guesses the memory
+ *     space of a pointer.
+ *   - stream arguments are hipStream_t passed as void*; NULL is the null stream.
+ *     Device calls are asynchronous on that stream unless stated otherwise;
+ *     arguments are validated on the host before anything is enqueued.
+ *   - Matrices are row-major and dense: element (i, j) of an [n][d] matrix is at
+ *     i*d + j.  Node ids are int32 in [0, N), N < 2^31; -1 marks an empty slot.
+ *   - Distances: squared Euclidean for PA_METRIC_L2, -<q, x> for PA_METRIC_IP;
+ *     smaller is better and ranks order by the key (distance, id).
+ *   - Buffers passed in are borrowed for the duration of the call (or of the
+ *     stream work the call enqueues); outputs are caller-owned unless stated.
+ */
+#ifndef PILOTANN_H
+#define PILOTANN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pa_status;
+
+#define PA_OK 0
+#define PA_EINVAL (-1)       /* bad argument (shape, range, null pointer, layout) */
+#define PA_ESTATE (-2)       /* call out of order (e.g. search before build)      */
+#define PA_ENOMEM (-3)       /* host allocation failed                            */
+#define PA_EHBM (-4)         /* device allocation failed or over the HBM budget   */
+#define PA_EHIP (-5)         /* HIP runtime error (message has hipGetErrorString) */
+#define PA_ENONFINITE (-6)   /* NaN or Inf in an input that must be finite        */
+#define PA_EUNSUPPORTED (-7) /* valid request the build does not support          */
+#define PA_EINTERNAL (-8)    /* internal invariant violated                       */
+
+#define PA_METRIC_L2 0
+#define PA_METRIC_IP 1
+
+#define PA_F32 0  /* float32 */
+#define PA_F16 1  /* IEEE binary16, round-to-nearest-even from float32 */
+#define PA_BF16 2 /* bfloat16, round-to-nearest-even from float32 */
+
+#define PA_SAMPLE_UNIFORM 0
+#define PA_SAMPLE_SEED_EXPAND 1
+
+#define PA_MAX_EF 512    /* largest candidate-list size of the GPU traversal */
+#define PA_MAX_DEGREE 64 /* largest subgraph out-degree                       */
+#define PA_MAX_DR 256    /* largest reduced dimension                         */
+
+/* ------------------------------------------------------------------ misc */
+
+/* Message of the last failed call on this thread ("" if none).  Owned by the library. */
+const char* pa_last_error(void);
+
+/* ABI version; bumped whenever a declaration below changes. */
+int32_t pa_abi_version(void);
+
+/* Make `device` current for the calling thread and initialise the library on it.
+ * PA_EHIP if the device does not exist or is not gfx950 (PA_EUNSUPPORTED). */
+pa_status pa_device_init(int32_t device);
+
+/* ------------------------------------------------- projection (section 4.1) */
+
+/* FP64 second-moment accumulation for the SVD projection (section 4.1: X = U S V^T,
+ * V^T V = I).  G_dev [D][D] (fp64) += X^T X and colsum_dev [D] (fp64) += sum of rows,
+ * over the n rows of X_dev [n][D] (fp32).  With accumulate = 0 both outputs are
+ * overwritten instead, so a large X can be streamed in chunks.  The summation order is
+ * fixed (deterministic).  D <= 1024. */
+pa_status pa_gram_f64(const float* X_dev, int64_t n, int32_t D, double* G_dev,
+                      double* colsum_dev, int32_t accumulate, void* stream);
+
+/* Symmetric eigendecomposition in FP64 on the host (cyclic Jacobi).  A_host [D][D]
+ * symmetric (only read); evals_host [D] descending; evecs_host [D][D] with column j the
+ * eigenvector of evals[j], each column signed so that its entry of largest magnitude is
+ * positive (ties up to rounding: the lowest row).  Blocking.  D <= 1024. */
+pa_status pa_eigh_f64(const double* A_host, int32_t D, double* evals_host, double* evecs_host);
+
+/* Fit the projection (section 4.1): streams X_host [N][D] (fp32, pageable or pinned)
+ * through the GPU in chunks, accumulates the FP64 second moment, centres it when
+ * center != 0 (covariance about the mean; used for L2) and keeps the d_r leading
+ * eigenvectors.  Outputs (host, caller-owned): V_host [D][d_r] fp32 (x_r = x^T V),
+ * evals_host [D] fp64 descending (of the possibly centred moment divided by N),
+ * mean_host [D] fp64.  Blocking.  PA_ENONFINITE if X holds NaN/Inf. */
+pa_status pa_fit_projection(const float* X_host, int64_t N, int32_t D, int32_t d_r,
+                            int32_t center, float* V_host, double* evals_host,
+                            double* mean_host);
+
+/* Y_dev [n][d_r] = X_dev [n][D] * V_dev [D][d_r] on MFMA (fp32 inputs, fp32 accumulate),
+ * stored as y_dtype (PA_F32 / PA_F16 / PA_BF16, round-to-nearest-even).  The reduced
+ * vectors x_primary of section 4.1.  d_r % 16 == 0, d_r <= PA_MAX_DR, D <= 4096. */
+pa_status pa_project(const float* X_dev, int64_t n, int32_t D, const float* V_dev,
+                     int32_t d_r, void* Y_dev, int32_t y_dtype, void* stream);
+
+/* Query projection fused with FES routing (section 5: a query is routed to the cluster
+ * whose centroid is nearest).  Qr_dev [m][d_r] fp32 = Q_dev [m][D] * V_dev; cluster_dev
+ * [m] int32 = argmin_c ||q_r - centroid_c||^2 over centroids_dev [r][d_r] (fp32), ties
+ * to the lowest c.  1 <= r <= 64. */
+pa_status pa_project_route(const float* Q_dev, int64_t m, int32_t D, const float* V_dev,
+                           int32_t d_r, const float* centroids_dev, int32_t r, float* Qr_dev,
+                           int32_t* cluster_dev, void* stream);
+
+/* ---------------------------------------- sampling and subgraph (sections 4.1, 4.3) */
+
+/* Node sampling (section 4.1): seeds taken in the given order (order_host: a permutation
+ * of [0, N), int64); PA_SAMPLE_SEED_EXPAND adds each new seed and then its
+ * out-neighbours in stored order, PA_SAMPLE_UNIFORM takes the first n_target seeds.
+ * Stops exactly at n_target nodes.  Full graph as CSR (rowptr_host [N+1] int64,
+ * nbrs_host int32).  mask_host [N] uint8 receives 1 for sampled nodes.  Host only. */
+pa_status pa_sample_nodes(int64_t N, const int64_t* rowptr_host, const int32_t* nbrs_host,
+                          const int64_t* order_host, int64_t n_target, int32_t mode,
+                          uint8_t* mask_host);
+
+/* Validate a reconnected subgraph (section 4.3 layout): CSR over all N rows; rows of
+ * unsampled nodes (mask_host[v] == 0) are empty, no edge enters an unsampled node, no
+ * self loops, no duplicate neighbours, out-degree <= R, ids in range.  PA_OK if valid,
+ * PA_EINVAL naming the first violation otherwise.  Host only. */
+pa_status pa_check_subgraph(int64_t N, const int64_t* rowptr_host, const int32_t* nbrs_host,
+                            const uint8_t* mask_host, int32_t R);
+
+/* Pack a CSR graph into the device traversal layout: adj_dev [N][R] int32, row v holds
+ * v's out-neighbours in stored order followed by -1 padding.  Node ids are unchanged
+ * (zero-degree rows stay, section 4.3).  PA_EINVAL if a row exceeds R or an id is out of
+ * range.  Blocking (the host staging copy is released on return). */
+pa_status pa_pack_adjacency(int64_t N, const int64_t* rowptr_host, const int32_t* nbrs_host,
+                            int32_t R, int32_t* adj_dev, void* stream);
+
+/* -------------------------------------------- fast entry selection (section 5) */
+
+/* Coarse clustering of the entry vectors (section 5: r equal buckets, the layout
+ * EV[r][n/r][d] of Algorithm 2), FP64 on the host: Lloyd iterations in squared L2 from
+ * the seeds init_host [r] (distinct positions in [0, n_p)), then a balanced assignment
+ * in the order of (distance, pivot position, cluster) that fills every bucket with exactly
+ * n_p / r pivots, then centroids = bucket means.  P_host [n_p][d] fp32 (pivot reduced
+ * vectors).  Outputs: buckets_host [r][n_p/r] int32 pivot positions (ascending within a
+ * bucket), centroids_host [r][d] fp32.  n_p % r == 0.  Blocking, deterministic. */
+pa_status pa_build_entries(const float* P_host, int32_t n_p, int32_t d, int32_t r,
+                           const int32_t* init_host, int32_t iters, int32_t* buckets_host,
+                           float* centroids_host);
+
+/* FES scoring and top-E (Algorithm 2 with a fused top-E): every query i is scored only
+ * against the n_b pivots of its cluster cluster_dev[i] (from pa_project_route), on MFMA:
+ * delta = ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP), fp32.  EV_dev [r][n_b][d] fp32
+ * bucket-major pivot vectors, EVnorm_dev [r][n_b] fp32 squared norms, EVid_dev [r][n_b]
+ * int32 node ids.  Outputs ids_dev [m][E] int32 and d_dev [m][E] fp32 ordered by
+ * (delta, id), padded with (-1, +inf) when E > n_b.  d % 16 == 0; the 16-query tile
+ * (16*d fp32 + 16*next_pow2(n_b) keys) must fit 64 KiB of LDS (n_b <= 512 at d <= 128),
+ * PA_EUNSUPPORTED otherwise.
+ * Results of a query do not depend on the other queries of the batch. */
+pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int64_t m,
+                            int32_t d, const float* EV_dev, const float* EVnorm_dev,
+                            const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
+                            int32_t metric, int32_t* ids_dev, float* d_dev, void* stream);
+
+/* ----------------------------------------------- stage 1: GPU piloting (4.1, Alg. 1) */
+
+/* Batched Algorithm 1 on the subgraph with reduced vectors, one 64-lane wavefront per
+ * query.  Qr_dev [m][d_r] fp32 reduced queries; Xr_dev [N][d_r] reduced base vectors of
+ * xr_dtype (rows 16-byte aligned: d_r*sizeof % 16 == 0); adj_dev [N][R] (pa_pack_adjacency);
+ * entries_dev [m][E] int32 (-1 skipped; ids outside [0, N) are skipped).  Outputs:
+ * ids_dev/d_dev [m][ef] - the final candidate list C in (delta, id) order, padded with
+ * (-1, +inf); counters_dev [m][4] int32 = (expansions, distance evaluations,
+ * visited-cache resets, 0).  The result equals Algorithm 1 with an exact visited set; the
+ * distance-evaluation count equals |visited| when no reset happened; counters[i][3] is a
+ * termination-guard flag (0).  1 <= ef <= PA_MAX_EF,
+ * 1 <= R <= PA_MAX_DEGREE.  cache_log2 selects the per-query LDS visited-cache size
+ * (2^cache_log2 entries, 8..13; 0 = automatic).  Xr_dev must hold N rows.
+ * counters_dev[i][3] is 1 if the query stopped at the N-expansion guard (never expected). */
+pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
+                          int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
+                          const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
+                          int32_t cache_log2, int32_t* ids_dev, float* d_dev,
+                          int32_t* counters_dev, void* stream);
+
+/* ------------------------------------------- stages 2 and 3 on the host (4.1) */
+
+/* Residual refinement (stage 2) and final traversal (stage 3) for m queries, on host
+ * threads.  X_host [N][D] fp32 full vectors; sub_adj_host [N][R_sub] and full_adj_host
+ * [N][R_full] int32 padded rows (-1); Q_host [m][D] fp32; beam_host [m][n_beam] int32
+ * stage-1 candidate ids (-1 skipped).  Stage 2 scores the beam with full distances, keeps
+ * the best ef_cpu, runs refine_steps Algorithm-1 steps on the subgraph and passes its
+ * candidates (all unchecked) and visited set to stage 3, which runs Algorithm 1 on the
+ * full graph with list size max(ef_cpu, k).  With refine_steps < 0 stage 2 is skipped
+ * (the beam is re-scored and handed on directly).  Outputs out_ids_host [m][k] int64,
+ * out_d_host [m][k] fp32 padded with (-1, +inf); counters_host [m][4] int32 (nullable)
+ * = (stage-2 distances, stage-3 distances, stage-3 expansions, 0).  threads <= 0 uses
+ * every host core.  Blocking. */
+pa_status pa_cpu_stages(const float* X_host, int64_t N, int32_t D, const int32_t* sub_adj_host,
+                        int32_t R_sub, const int32_t* full_adj_host, int32_t R_full,
+                        const float* Q_host, int64_t m, const int32_t* beam_host,
+                        int32_t n_beam, int32_t ef_cpu, int32_t k, int32_t refine_steps,
+                        int32_t metric, int32_t threads, int64_t* out_ids_host,
+                        float* out_d_host, int32_t* counters_host);
+
+/* Plain Algorithm 1 on the full graph from given entries (the graceful-degradation mode
+ * of section 4.1: stage 3 alone).  entries_host [m][E] int32.  Outputs as
+ * pa_cpu_stages; counters = (0, distances, expansions, 0).  Blocking. */
+pa_status pa_cpu_search(const float* X_host, int64_t N, int32_t D, const int32_t* full_adj_host,
+                        int32_t R_full, const float* Q_host, int64_t m,
+                        const int32_t* entries_host, int32_t E, int32_t ef, int32_t k,
+                        int32_t metric, int32_t threads, int64_t* out_ids_host,
+                        float* out_d_host, int32_t* counters_host);
+
+/* ------------------------------------------------------ index and pipeline */
+
+typedef struct pa_index pa_index;
+
+typedef struct {
+    int32_t dim;          /* D: full dimension                                   */
+    int32_t d_r;          /* reduced dimension (multiple of 16)                  */
+    int32_t metric;       /* PA_METRIC_L2 / PA_METRIC_IP                         */
+    int32_t xr_dtype;     /* storage type of the reduced base vectors            */
+    int32_t r;            /* FES clusters (the paper uses 32)                    */
+    int32_t refine_steps; /* stage-2 traversal steps (the paper uses 2)          */
+    int32_t threads;      /* host threads for stages 2-3 (<= 0: all cores)       */
+    int32_t device;       /* HIP device ordinal                                  */
+    int64_t hbm_budget;   /* bytes of HBM the index and search buffers may use (0 = no limit) */
+} pa_params;
+
+/* Create an empty index.  params is copied.  *out receives the handle (library-owned;
+ * release with pa_index_destroy). */
+pa_status pa_index_create(const pa_params* params, pa_index** out);
+pa_status pa_index_destroy(pa_index* idx);
+
+/* Attach the full data (section 3: the full index stays in host RAM).  X_host [N][D] fp32
+ * is BORROWED until destroy (stages 2-3 read it); the full graph CSR is copied into a
+ * padded host table [N][max degree] (max degree <= 1024). */
+pa_status pa_index_set_data(pa_index* idx, const float* X_host, int64_t N,
+                            const int64_t* rowptr_host, const int32_t* nbrs_host);
+
+/* Fit the projection on the attached X (pa_fit_projection) and write the reduced base
+ * vectors of all N rows to HBM in xr_dtype.  center: 1 centred, 0 uncentred, -1 the
+ * metric's default (centred for L2, uncentred for IP). */
+pa_status pa_index_fit_projection(pa_index* idx, int32_t center);
+
+/* Use a caller-supplied projection V_host [D][d_r] fp32 instead of fitting one. */
+pa_status pa_index_set_projection(pa_index* idx, const float* V_host);
+
+/* Sampling on the attached full graph (pa_sample_nodes). */
+pa_status pa_index_sample_nodes(pa_index* idx, const int64_t* order_host, int64_t n_target,
+                                int32_t mode, uint8_t* mask_host);
+
+/* build_subgraph: validate (pa_check_subgraph against mask_host) and upload the
+ * reconnected subgraph; a host copy is kept for stage 2. */
+pa_status pa_index_build_subgraph(pa_index* idx, const uint8_t* mask_host,
+                                  const int64_t* rowptr_host, const int32_t* nbrs_host);
+
+/* build_entries: cluster the pivots pivot_ids_host [n_p] (node ids, each with out-edges in
+ * the subgraph) on their reduced vectors as stored in HBM (pa_build_entries), and upload
+ * the bucket-major entry table.  init_host [r] seeds, iters Lloyd iterations. */
+pa_status pa_index_build_entries(pa_index* idx, const int32_t* pivot_ids_host, int32_t n_p,
+                                 const int32_t* init_host, int32_t iters);
+
+/* Copy out index state for inspection: V_host [D][d_r]; buckets_host [r][n_p/r] node ids;
+ * centroids_host [r][d_r]; any pointer may be NULL. */
+pa_status pa_index_get_state(const pa_index* idx, float* V_host, int32_t* buckets_host,
+                             float* centroids_host);
+
+/* Device pointers of the index's tables (for stage-isolated calls); any may be NULL. */
+pa_status pa_index_device_tables(const pa_index* idx, const void** Xr_dev,
+                                 const int32_t** adj_dev, const float** V_dev,
+                                 const float** centroids_dev, const float** EV_dev,
+                                 const float** EVnorm_dev, const int32_t** EVid_dev);
+
+typedef struct {
+    int32_t ef_gpu;       /* stage-1 list size (1..PA_MAX_EF)                     */
+    int32_t ef_cpu;       /* stage-2/3 list size                                   */
+    int32_t E;            /* entries per query (0: min(ef_gpu, n_p / r))           */
+    int32_t batch;        /* queries per pipelined sub-batch (0: automatic)        */
+    int32_t stage_mask;   /* bit 0 GPU stage, bit 1 refinement (0: both)           */
+    int32_t cache_log2;   /* GPU visited-cache size (0: automatic)                 */
+    int32_t threads;      /* host threads (0: index default)                       */
+    int32_t reserved;
+} pa_search_opts;
+
+typedef struct {
+    double wall_ms;          /* whole call                                          */
+    double beam_ms;          /* sum of stage-1 kernel durations (HIP events)        */
+    double fes_ms;           /* projection + routing + FES kernels (HIP events)     */
+    int64_t beam_launches;   /* stage-1 kernel launches                             */
+    int64_t n_exp1;          /* stage-1 expansions, summed over queries             */
+    int64_t n_dist1;         /* stage-1 distance evaluations                        */
+    int64_t n_dist2;         /* stage-2 distance evaluations                        */
+    int64_t n_dist3;         /* stage-3 distance evaluations                        */
+    int64_t n_exp3;          /* stage-3 expansions                                  */
+    int64_t n_reset1;        /* stage-1 visited-cache resets                        */
+    double host_wait_ms;     /* host time spent waiting for GPU batches             */
+} pa_search_stats;
+
+/* Full search (section 4.1 stages 1-3 with FES): Q_host [m][D] fp32 (pageable or
+ * pinned) -> out_ids_host [m][k] int64, out_d_host [m][k] fp32 (full squared L2 or
+ * -IP), padded with (-1, +inf).  Queries are split into sub-batches; stage 1 of batch b+1
+ * runs on the GPU while the host threads run stages 2-3 of batch b (section 4.2
+ * pipelining).  Blocking.  counters_host [m][8] int32 (nullable) = (n_exp1, n_dist1,
+ * reset1, n_dist2, n_dist3, n_exp3, 0, 0).  stats nullable.  PA_ESTATE before the
+ * projection, subgraph and entries are built. */
+pa_status pa_search(pa_index* idx, const float* Q_host, int64_t m, int32_t k,
+                    const pa_search_opts* opts, int64_t* out_ids_host, float* out_d_host,
+                    int32_t* counters_host, pa_search_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PILOTANN_H */

@@ -18,9 +18,12 @@ Inputs for the later stages: ``initial`` seeds C with already scored
 (distance, id) pairs, ``visited`` pre-populates the visited set and
 ``max_steps`` bounds the number of loop steps (the refinement stage runs two).
 
-The returned ``margin`` is the smallest relative gap between neighbouring keys
-among the first ef+1 positions of C over all steps: when it is tiny, a
-different rounding of the distances may legitimately change the path.
+The returned ``margin`` is the smallest relative gap over the comparisons that
+steer Algorithm 1: the first unchecked entry against the next unchecked one
+(which node line 5 expands), the last kept key against the first key dropped by
+each resize (line 11), and neighbouring keys of the final list (its order).
+When it is tiny, a different rounding of the distances may legitimately change
+the result.
 """
 
 from __future__ import annotations
@@ -30,13 +33,15 @@ import numpy as np
 from .metric import delta_many
 
 
-def _gap(sorted_keys, ef: int) -> float:
-    head = [d for d, _ in sorted_keys[:ef + 1]]
-    best = np.inf
-    for a, b in zip(head, head[1:]):
-        scale = max(abs(a), abs(b), 1e-300)
-        best = min(best, (b - a) / scale)
-    return best
+def _rel_gap(a: float, b: float) -> float:
+    return abs(b - a) / max(abs(a), abs(b), 1e-300)
+
+
+def _resize_gap(sorted_keys, ef: int) -> float:
+    """Gap at the resize boundary (kept key ef-1 against dropped key ef)."""
+    if len(sorted_keys) <= ef:
+        return np.inf
+    return _rel_gap(sorted_keys[ef - 1][0], sorted_keys[ef][0])
 
 
 def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "l2", *,
@@ -74,7 +79,7 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
         for d, v in zip(ds, fresh):
             C.append([(float(d), v), False])
     C.sort(key=lambda c: c[0])
-    margin = _gap([c[0] for c in C], ef)
+    margin = _resize_gap([c[0] for c in C], ef)
     del C[ef:]
     n_exp = 0
     while max_steps is None or n_exp < max_steps:
@@ -82,6 +87,9 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
         pos = next((i for i, c in enumerate(C) if not c[1]), None)
         if pos is None:
             break  # line 12: no unchecked node left
+        nxt = next((i for i in range(pos + 1, len(C)) if not C[i][1]), None)
+        if nxt is not None:
+            margin = min(margin, _rel_gap(C[pos][0][0], C[nxt][0][0]))
         C[pos][1] = True
         u = C[pos][0][1]
         n_exp += 1
@@ -98,9 +106,11 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
             for d, v in zip(ds, new):
                 C.append([(float(d), v), False])
             C.sort(key=lambda c: c[0])
-            margin = min(margin, _gap([c[0] for c in C], ef))
+            margin = min(margin, _resize_gap([c[0] for c in C], ef))
         # line 11: C.resize(ef)
         del C[ef:]
+    for a, b in zip(C, C[1:]):
+        margin = min(margin, _rel_gap(a[0][0], b[0][0]))
     return {
         "ids": np.asarray([c[0][1] for c in C], dtype=np.int64),
         "dists": np.asarray([c[0][0] for c in C], dtype=np.float64),

@@ -1,0 +1,209 @@
+// Fast entry selection (section 5, Algorithm 2, Table 2).
+//
+// Algorithm 2 assigns one block per cluster and skips, inside every block, the queries
+// routed elsewhere.  Here the queries are first grouped by their routed cluster (a
+// counting sort into a preallocated permutation - no allocation, as section 5 asks), and
+// then every block works on one (cluster, 16-query tile) pair: a 16 x n_b x d product on
+// MFMA against that cluster's bucket of pivots, the distance epilogue fused, and a top-E
+// per query taken from LDS.  The m x n distance matrix D of Algorithm 2 is never stored.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace pa {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTQ = 16;          // queries per tile (MFMA rows)
+constexpr int kMaxClusters = 64;
+constexpr int kMaxNbPow2 = 512;  // LDS holds 16 x 512 keys
+
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u ^ 0x80000000u) : ~u);
+}
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// scratch (int32): [0, r) counts | [r, 2r+1) offsets | [2r+1, 3r+2) tile prefix | perm[m]
+__global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__ cluster, int64_t m, int r,
+                                                     int32_t* __restrict__ scratch) {
+    __shared__ int cnt[kMaxClusters];
+    __shared__ int cur[kMaxClusters];
+    __shared__ int off[kMaxClusters + 1];
+    const int t = threadIdx.x;
+    if (t < kMaxClusters) {
+        cnt[t] = 0;
+        cur[t] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = t; i < m; i += 1024) {
+        const int c = cluster[i];
+        if (c >= 0 && c < r) atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int o = 0, tp = 0;
+        for (int c = 0; c < r; ++c) {
+            off[c] = o;
+            scratch[c] = cnt[c];
+            scratch[r + c] = o;
+            scratch[2 * r + 1 + c] = tp;
+            o += cnt[c];
+            tp += (cnt[c] + kTQ - 1) / kTQ;
+        }
+        off[r] = o;
+        scratch[2 * r] = o;
+        scratch[3 * r + 1] = tp;
+    }
+    __syncthreads();
+    int32_t* perm = scratch + 3 * r + 2;
+    for (int64_t i = t; i < m; i += 1024) {
+        const int c = cluster[i];
+        if (c >= 0 && c < r) perm[off[c] + atomicAdd(&cur[c], 1)] = static_cast<int32_t>(i);
+    }
+}
+
+__global__ __launch_bounds__(256) void score_kernel(const float* __restrict__ Qr, int d,
+                                                    const float* __restrict__ EV,
+                                                    const float* __restrict__ EVnorm,
+                                                    const int32_t* __restrict__ EVid, int r, int n_b,
+                                                    int nbp, int E, int metric,
+                                                    const int32_t* __restrict__ scratch,
+                                                    int32_t* __restrict__ out_ids, float* __restrict__ out_d) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float* Aq = reinterpret_cast<float*>(smem);                       // [kTQ][d]
+    float* qn = Aq + kTQ * d;                                         // [kTQ]
+    uint64_t* keys = reinterpret_cast<uint64_t*>(qn + kTQ + 2);       // [kTQ][nbp] (8-byte aligned)
+    __shared__ int qidx[kTQ];
+    __shared__ int s_c, s_cnt;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = t >> 6;
+    const int32_t* counts = scratch;
+    const int32_t* offsets = scratch + r;
+    const int32_t* tprefix = scratch + 2 * r + 1;
+    const int32_t* perm = scratch + 3 * r + 2;
+    const int b = blockIdx.x;
+    if (t == 0) {
+        int c = -1, cntq = 0;
+        if (b < tprefix[r]) {
+            c = 0;
+            while (c + 1 < r && tprefix[c + 1] <= b) ++c;
+            const int tile = b - tprefix[c];
+            const int base = offsets[c] + tile * kTQ;
+            cntq = min(kTQ, counts[c] - tile * kTQ);
+            for (int i = 0; i < kTQ; ++i) qidx[i] = (i < cntq) ? perm[base + i] : -1;
+        }
+        s_c = c;
+        s_cnt = cntq;
+    }
+    __syncthreads();
+    const int c = s_c;
+    if (c < 0) return;
+    const int cntq = s_cnt;
+    for (int idx = t; idx < kTQ * d; idx += 256) {
+        const int i = idx / d, j = idx - (idx / d) * d;
+        Aq[idx] = (i < cntq) ? Qr[static_cast<int64_t>(qidx[i]) * d + j] : 0.0f;
+    }
+    __syncthreads();
+    if (t < kTQ) {
+        float s = 0.0f;
+        for (int j = 0; j < d; ++j) s = __builtin_fmaf(Aq[t * d + j], Aq[t * d + j], s);
+        qn[t] = s;
+    }
+    __syncthreads();
+
+    const float* ev = EV + static_cast<int64_t>(c) * n_b * d;
+    const float* evn = EVnorm + static_cast<int64_t>(c) * n_b;
+    const int32_t* evid = EVid + static_cast<int64_t>(c) * n_b;
+    const int nblk = (nbp + 15) / 16;
+    for (int pb = w; pb < nblk; pb += 4) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int p = pb * 16 + (lane & 15);
+        const bool pv = p < n_b;
+        for (int k = 0; k < d; k += 4) {
+            const float a = Aq[(lane & 15) * d + k + (lane >> 4)];
+            const float bb = pv ? ev[static_cast<int64_t>(p) * d + k + (lane >> 4)] : 0.0f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 4 * (lane >> 4) + i;
+            uint64_t key = ~0ull;
+            if (pv && p < nbp) {
+                const float dot = acc[i];
+                const float dist = (metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[row] + evn[p]) : -dot;
+                key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(evid[p]);
+            }
+            if (p < nbp) keys[row * nbp + p] = key;
+        }
+    }
+    __syncthreads();
+
+    // top-E per query: bitonic sort of the row's keys by one wave, then the first E
+    for (int row = w; row < cntq; row += 4) {
+        uint64_t* s = keys + row * nbp;
+        for (int k = 2; k <= nbp; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = lane; i < nbp; i += 64) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t x = s[i], y = s[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            s[i] = y;
+                            s[l] = x;
+                        }
+                    }
+                }
+                wave_sync();
+            }
+        }
+        const int64_t q = qidx[row];
+        for (int e = lane; e < E; e += 64) {
+            int32_t id = -1;
+            float dist = __builtin_huge_valf();
+            if (e < n_b) {
+                const uint64_t key = s[e];
+                id = static_cast<int32_t>(key & 0xFFFFFFFFu);
+                dist = unord_f32(static_cast<uint32_t>(key >> 32));
+            }
+            out_ids[q * E + e] = id;
+            out_d[q * E + e] = dist;
+        }
+    }
+}
+
+}  // namespace
+
+size_t select_entries_scratch_ints(int64_t m, int r) { return static_cast<size_t>(3 * r + 2 + m); }
+
+void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
+                           const float* EVnorm, const int32_t* EVid, int r, int n_b, int E, int metric,
+                           int32_t* ids, float* dists, int32_t* scratch_i32, hipStream_t s) {
+    if (m == 0) return;
+    require(r >= 1 && r <= kMaxClusters, "FES supports 1..64 clusters");
+    int nbp = 1;
+    while (nbp < n_b) nbp <<= 1;
+    if (nbp < 16) nbp = 16;
+    require(nbp <= kMaxNbPow2, "FES bucket size above 512 is not supported by this build", PA_EUNSUPPORTED);
+    hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
+    PA_HIP(hipGetLastError());
+    const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
+    const size_t lds = sizeof(float) * (kTQ * d + kTQ + 2) + sizeof(uint64_t) * kTQ * nbp;
+    require(lds <= 64 * 1024, "FES tile does not fit in 64 KiB of LDS (bucket too large for d)", PA_EUNSUPPORTED);
+    hipLaunchKernelGGL(score_kernel, dim3(max_tiles), dim3(256), lds, s, Qr, d, EV, EVnorm, EVid, r, n_b,
+                       nbp, E, metric, scratch_i32, ids, dists);
+    PA_HIP(hipGetLastError());
+}
+
+}  // namespace pa

@@ -1,0 +1,234 @@
+// Projection to the SVD subspace (section 4.1: x_primary = x^T V_d) on MFMA, the FES
+// routing of a reduced query to its nearest coarse centroid (section 5), and the FP64
+// second-moment accumulation that fixes V (the only FP64 work on the GPU).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace pa {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- projection GEMM
+// Block: 256 threads = 4 waves, 64 output rows x all d_r columns.  The K loop stages a
+// 64x16 slice of X and a 16 x d_r slice of V in LDS; each wave multiplies its 16 rows with
+// v_mfma_f32_16x16x4_f32 (A: lane l holds A[l%16][l/16]; B: lane l holds B[l/16][l%16];
+// D: lane l holds rows 4*(l/16)..+3 of column l%16).
+constexpr int kBM = 64;
+constexpr int kBK = 16;
+
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float v) {
+    _Float16 h = static_cast<_Float16>(v);  // round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7F800000u) == 0x7F800000u) {  // Inf / NaN: keep class, quiet NaN
+        return static_cast<uint16_t>((u >> 16) | ((u & 0x007FFFFFu) ? 0x40u : 0u));
+    }
+    uint32_t rounding = 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>((u + rounding) >> 16);
+}
+
+__global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ X, int64_t n, int D,
+                                                      const float* __restrict__ V, int d_r, void* Y,
+                                                      int y_dtype) {
+    __shared__ float As[kBM][kBK + 1];
+    __shared__ float Bs[kBK][PA_MAX_DR + 4];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int w = t >> 6;
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kBM;
+    const int nb = d_r >> 4;
+    f32x4 acc[PA_MAX_DR / 16];
+#pragma unroll
+    for (int c = 0; c < PA_MAX_DR / 16; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < D; k0 += kBK) {
+        {
+            const int r = t >> 2;
+            const int c = (t & 3) * 4;
+            const int64_t gr = row0 + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = k0 + c + e;
+                As[r][c + e] = (gr < n && k < D) ? X[gr * D + k] : 0.0f;
+            }
+        }
+        for (int idx = t; idx < kBK * d_r; idx += 256) {
+            const int kk = idx / d_r;
+            const int j = idx - kk * d_r;
+            Bs[kk][j] = (k0 + kk < D) ? V[static_cast<int64_t>(k0 + kk) * d_r + j] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+            const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int c = 0; c < PA_MAX_DR / 16; ++c) {
+                if (c < nb) {
+                    const float b = Bs[kk + (lane >> 4)][c * 16 + (lane & 15)];
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < PA_MAX_DR / 16; ++c) {
+        if (c >= nb) continue;
+        const int col = c * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = row0 + w * 16 + 4 * (lane >> 4) + i;
+            if (row >= n) continue;
+            const float v = acc[c][i];
+            const int64_t off = row * d_r + col;
+            if (y_dtype == PA_F32) static_cast<float*>(Y)[off] = v;
+            else if (y_dtype == PA_F16) static_cast<uint16_t*>(Y)[off] = f32_to_f16_bits(v);
+            else static_cast<uint16_t*>(Y)[off] = f32_to_bf16_bits(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- routing
+// One wave per query: lane c < r scores centroid c with a sequential fp32 sum of squared
+// differences; the wave takes the minimum (ties to the lowest c).
+__global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Qr, int64_t m, int d_r,
+                                                    const float* __restrict__ C, int r,
+                                                    int32_t* __restrict__ cluster) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (q >= m) return;
+    const float* qv = Qr + q * d_r;
+    float best = __builtin_huge_valf();
+    if (lane < r) {
+        const float* cv = C + static_cast<int64_t>(lane) * d_r;
+        float s = 0.0f;
+        for (int j = 0; j < d_r; ++j) {
+            const float d = qv[j] - cv[j];
+            s = __builtin_fmaf(d, d, s);
+        }
+        best = s;
+    }
+    // (distance, index) minimum across the wave, lowest index on ties
+    uint64_t key = (static_cast<uint64_t>(__float_as_uint(best)) << 32) | static_cast<uint32_t>(lane);
+    if (lane >= r) key = ~0ull;
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+    }
+    if (lane == 0) cluster[q] = static_cast<int32_t>(key & 0xFFFFFFFFu);
+}
+
+// ---------------------------------------------------------------- FP64 second moment
+// partial[chunk][i][j] = sum over the chunk's rows of x_i x_j (32x32 tile per block,
+// rows consumed in order of increasing index); colsum partials likewise; a second pass sums
+// the chunk partials in chunk order, so the result does not depend on scheduling.
+constexpr int kGT = 32;
+
+__global__ __launch_bounds__(256) void gram_partial_kernel(const float* __restrict__ X, int64_t n, int D,
+                                                           int64_t rows_per_chunk,
+                                                           double* __restrict__ partial) {
+    __shared__ double A[kGT][kGT + 1];
+    __shared__ double B[kGT][kGT + 1];
+    const int ti = blockIdx.x, tj = blockIdx.y, chunk = blockIdx.z;
+    const int t = threadIdx.x;
+    const int a = t >> 3;         // row of the G tile
+    const int b = (t & 7) * 4;    // first of 4 columns
+    const int64_t r_begin = static_cast<int64_t>(chunk) * rows_per_chunk;
+    const int64_t r_end = r_begin + rows_per_chunk < n ? r_begin + rows_per_chunk : n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGT) {
+        for (int idx = t; idx < kGT * kGT; idx += 256) {
+            const int rr = idx / kGT, cc = idx % kGT;
+            const int64_t row = r0 + rr;
+            const int ca = ti * kGT + cc, cb = tj * kGT + cc;
+            const bool ok = row < r_end;
+            A[rr][cc] = (ok && ca < D) ? static_cast<double>(X[row * D + ca]) : 0.0;
+            B[rr][cc] = (ok && cb < D) ? static_cast<double>(X[row * D + cb]) : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < kGT; ++rr) {
+            const double va = A[rr][a];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = __builtin_fma(va, B[rr][b + e], acc[e]);
+        }
+        __syncthreads();
+    }
+    const int gi = ti * kGT + a;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int gj = tj * kGT + b + e;
+        if (gi < D && gj < D) partial[(static_cast<int64_t>(chunk) * D + gi) * D + gj] = acc[e];
+    }
+}
+
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ X, int64_t n, int D,
+                                                             int64_t rows_per_chunk,
+                                                             double* __restrict__ partial) {
+    const int chunk = blockIdx.y;
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= D) return;
+    const int64_t r_begin = static_cast<int64_t>(chunk) * rows_per_chunk;
+    const int64_t r_end = r_begin + rows_per_chunk < n ? r_begin + rows_per_chunk : n;
+    double s = 0.0;
+    for (int64_t r = r_begin; r < r_end; ++r) s += static_cast<double>(X[r * D + col]);
+    partial[static_cast<int64_t>(chunk) * D + col] = s;
+}
+
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const double* __restrict__ partial, int chunks,
+                                                         int64_t len, double* __restrict__ out,
+                                                         int accumulate) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += partial[static_cast<int64_t>(c) * len + i];
+    out[i] = accumulate ? out[i] + s : s;
+}
+
+}  // namespace
+
+void launch_project(const float* X, int64_t n, int D, const float* V, int d_r, void* Y, int y_dtype,
+                    const float* centroids, int r, int32_t* cluster, hipStream_t s) {
+    if (n == 0) return;
+    const int blocks = static_cast<int>((n + kBM - 1) / kBM);
+    hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, s, X, n, D, V, d_r, Y, y_dtype);
+    PA_HIP(hipGetLastError());
+    if (centroids != nullptr) {
+        const int rb = static_cast<int>((n + 3) / 4);
+        hipLaunchKernelGGL(route_kernel, dim3(rb), dim3(256), 0, s, static_cast<const float*>(Y), n, d_r,
+                           centroids, r, cluster);
+        PA_HIP(hipGetLastError());
+    }
+}
+
+void launch_gram_f64(const float* X, int64_t n, int D, double* G, double* colsum, bool accumulate,
+                     hipStream_t s) {
+    int chunks = static_cast<int>((n + 4095) / 4096);
+    if (chunks > 64) chunks = 64;
+    if (chunks < 1) chunks = 1;
+    const int64_t rows_per_chunk = (n + chunks - 1) / chunks;
+    const int64_t dd = static_cast<int64_t>(D) * D;
+    double* part = nullptr;
+    PA_HIP(hipMallocAsync(reinterpret_cast<void**>(&part),
+                          sizeof(double) * (static_cast<size_t>(chunks) * dd + static_cast<size_t>(chunks) * D), s));
+    double* part_cs = part + static_cast<int64_t>(chunks) * dd;
+    const int tiles = (D + kGT - 1) / kGT;
+    hipLaunchKernelGGL(gram_partial_kernel, dim3(tiles, tiles, chunks), dim3(256), 0, s, X, n, D,
+                       rows_per_chunk, part);
+    PA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((D + 255) / 256, chunks), dim3(256), 0, s, X, n, D,
+                       rows_per_chunk, part_cs);
+    PA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(static_cast<int>((dd + 255) / 256)), dim3(256), 0, s, part,
+                       chunks, dd, G, accumulate ? 1 : 0);
+    PA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3((D + 255) / 256), dim3(256), 0, s, part_cs, chunks,
+                       static_cast<int64_t>(D), colsum, accumulate ? 1 : 0);
+    PA_HIP(hipGetLastError());
+    PA_HIP(hipFreeAsync(part, s));
+}
+
+}  // namespace pa

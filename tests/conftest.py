@@ -16,3 +16,11 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+def pytest_sessionstart(session):
+    """Build the library once if it is missing (hipcc cross-compiles without a GPU)."""
+    lib = os.path.join(ROOT, "paper_2503_21206_amd", "libpilotann.so")
+    if not os.path.exists(lib):
+        from paper_2503_21206_amd.build import build
+        build()

@@ -1,0 +1,221 @@
+"""The C-ABI library: it loads, exports every declared symbol, and its host-only
+entry points (sampling, subgraph validation, clustering, eigensolver, stages
+2-3) agree with the oracle.  No GPU needed."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2503_21206_amd as pa
+from synth.data import gmm_points, make_rng
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return pa.lib()
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            names |= set(re.findall(r"^\s*(?:pa_status|const char\*|int32_t)\s+(pa_[a-z0-9_]+)\s*\(", text, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported(L):
+    decl = _declared()
+    assert len(decl) >= 25
+    for name in decl:
+        assert hasattr(L, name), name
+    assert decl == set(pa.symbols())
+    assert pa.abi_version() == 1
+
+
+def _csr(rows):
+    rowptr = [0]
+    flat = []
+    for r in rows:
+        flat.extend(r)
+        rowptr.append(len(flat))
+    return np.asarray(rowptr, dtype=np.int64), np.asarray(flat, dtype=np.int32)
+
+
+def test_sample_nodes_matches_oracle(golden_dir):
+    import json
+    g = json.load(open(os.path.join(golden_dir, "sampling_examples.json")))
+    rowptr, nbrs = _csr(g["rows"])
+    for c in g["cases"]:
+        m = pa.sample_nodes(rowptr, nbrs, g["order"], c["n_target"], c["mode"])
+        assert np.nonzero(m)[0].tolist() == c["members"]
+    from synth.graph import build_graph, padded_to_csr
+    X = gmm_points(101, 800, 8, 4)
+    rp, nb = padded_to_csr(build_graph(X, 10, device="cpu"))
+    order = make_rng(7, 0).permutation(800)
+    for mode in ("uniform", "seed_expand"):
+        for t in (0, 1, 199, 800):
+            a = pa.sample_nodes(rp, nb, order, t, mode)
+            b = oracle.sample_nodes(rp, nb, order, t, mode)
+            assert (a == b).all()
+
+
+def test_sample_nodes_rejects_bad_input():
+    rowptr, nbrs = _csr([[1], [0]])
+    with pytest.raises(pa.PilotannError) as e:
+        pa.sample_nodes(rowptr, nbrs, [0, 1], 3)
+    assert e.value.status == -1
+    with pytest.raises(pa.PilotannError):
+        pa.sample_nodes(rowptr, nbrs, [0, 0], 2, "uniform")  # not a permutation
+
+
+def test_check_subgraph_accepts_valid_and_names_violations():
+    from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
+    X = gmm_points(102, 500, 8, 3)
+    rp, nb = padded_to_csr(build_graph(X, 10, device="cpu"))
+    order = make_rng(8, 0).permutation(500)
+    mask = oracle.sample_nodes(rp, nb, order, 125, "seed_expand")
+    sr, sn = build_subgraph_csr(X, mask, 10, device="cpu")
+    pa.check_subgraph(sr, sn, mask, 10)
+    u = int(np.nonzero(mask)[0][0])
+    outside = int(np.nonzero(~mask)[0][0])
+    bad = sn.copy()
+    bad[sr[u]] = outside
+    with pytest.raises(pa.PilotannError, match="unsampled"):
+        pa.check_subgraph(sr, bad, mask, 10)
+    bad = sn.copy()
+    bad[sr[u]] = u
+    with pytest.raises(pa.PilotannError, match="self loop"):
+        pa.check_subgraph(sr, bad, mask, 10)
+    with pytest.raises(pa.PilotannError, match="degree"):
+        pa.check_subgraph(sr, sn, mask, 1)
+
+
+def test_build_entries_matches_oracle_buckets():
+    P = gmm_points(103, 1024, 16, 20)
+    init = make_rng(9, 1).choice(1024, 32, replace=False)
+    b, c = pa.build_entries(P, 32, init, 10)
+    ob, oc = oracle.balanced_kmeans(P, 32, init, 10)
+    assert (b == ob).all()
+    np.testing.assert_allclose(c, oc, rtol=1e-6, atol=1e-6)
+
+
+def test_build_entries_hand_example(golden_dir):
+    import json
+    g = json.load(open(os.path.join(golden_dir, "entries_example.json")))
+    b, c = pa.build_entries(np.array(g["pivots"], dtype=np.float32), g["r"], g["init"], g["iters"])
+    assert b.tolist() == g["buckets"]
+    np.testing.assert_allclose(c, g["centroids"], atol=1e-6)
+
+
+def test_eigh_matches_oracle_and_hand_example(golden_dir):
+    import json
+    g = json.load(open(os.path.join(golden_dir, "projection_axes.json")))
+    M, _ = oracle.projection.second_moment(np.array(g["points"]), True)
+    w, V = pa.eigh_f64(M)
+    np.testing.assert_allclose(w, g["eigenvalues"], atol=1e-12)
+    np.testing.assert_allclose(V[:, :2], g["V"], atol=1e-12)
+    X = gmm_points(104, 2000, 24, 30) + 1.0
+    M, _ = oracle.projection.second_moment(X, True)
+    w, V = pa.eigh_f64(M)
+    Vo, wo, _ = oracle.fit_projection(X, 24)
+    np.testing.assert_allclose(w, wo, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(V.T @ V, np.eye(24), atol=1e-12)
+    # eigenvectors agree up to the shared sign rule where eigenvalues are separated
+    gaps = np.minimum(np.abs(np.diff(wo, prepend=np.inf)), np.abs(np.diff(wo, append=-np.inf)))
+    for j in range(24):
+        if gaps[j] > 1e-6 * wo[0]:
+            np.testing.assert_allclose(V[:, j], Vo[:, j], atol=1e-8)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    from synth import SPECS, base_vectors, query_vectors
+    from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
+    s = SPECS["tiny"]
+    X = base_vectors(s)
+    Q = query_vectors(s, 60)
+    adj = build_graph(X, 32, device="cpu")
+    rp, nb = padded_to_csr(adj)
+    order = make_rng(s.seed + 3, 0).permutation(s.n)
+    mask = oracle.sample_nodes(rp, nb, order, round(s.rho * s.n), s.sample_mode)
+    sr, sn = build_subgraph_csr(X, mask, 32, device="cpu")
+    return dict(X=X, Q=Q, rp=rp, nb=nb, adj=adj, mask=mask, sr=sr, sn=sn,
+                sub_adj=oracle.padded_from_csr(sr, sn, 32))
+
+
+def _near_tie_ok(ids, ref_ids, margin, thr=2e-5):
+    return (ids == ref_ids).all() or margin < thr
+
+
+def test_cpu_stages_match_oracle(tiny):
+    X, Q = tiny["X"], tiny["Q"]
+    rng = make_rng(11, 0)
+    S = np.nonzero(tiny["mask"])[0]
+    beams = np.stack([rng.choice(S, 48, replace=False) for _ in range(Q.shape[0])]).astype(np.int32)
+    beams[:, -3:] = -1  # padding is skipped
+    for steps, ef_cpu, k in ((2, 32, 10), (0, 16, 10), (-1, 24, 30)):
+        ids, d, cnt = pa.cpu_stages(X, tiny["sub_adj"], tiny["adj"], Q, beams, ef_cpu, k, steps, threads=4)
+        bad = 0
+        for i in range(Q.shape[0]):
+            if steps >= 0:
+                r = oracle.refine(Q[i], X, tiny["sr"], tiny["sn"], beams[i], ef_cpu, steps=steps)
+                c_ids, c_d, vis, n2 = r["ids"], r["dists"], r["visited"], r["n_dist"]
+            else:
+                b = beams[i][beams[i] >= 0]
+                c_d = oracle.delta_many(Q[i], X[b])
+                c_ids, vis, n2 = b, set(b.tolist()), b.size
+            oi, od, f = oracle.final_traversal(Q[i], X, tiny["rp"], tiny["nb"], c_ids, c_d, vis, ef_cpu, k)
+            same = (ids[i] == oi).all()
+            if not same:
+                bad += 1
+                continue
+            np.testing.assert_allclose(d[i], od, rtol=2e-6)
+            assert cnt[i, 0] == n2 and cnt[i, 1] == f["n_dist"] and cnt[i, 2] == f["n_exp"]
+        assert bad <= max(1, Q.shape[0] // 1000), bad
+
+
+def test_cpu_search_is_plain_greedy_search(tiny):
+    X, Q = tiny["X"], tiny["Q"]
+    entries = np.tile(np.array([0, 4000, 9999], dtype=np.int32), (Q.shape[0], 1))
+    ids, d, cnt = pa.cpu_search(X, tiny["adj"], Q, entries, 40, 10, threads=3)
+    for i in range(Q.shape[0]):
+        r = oracle.greedy_search(Q[i], X, tiny["rp"], tiny["nb"], 40, entries[i])
+        if (ids[i] == r["ids"][:10]).all():
+            assert cnt[i, 1] == r["n_dist"] and cnt[i, 2] == r["n_exp"]
+            np.testing.assert_allclose(d[i], r["dists"][:10], rtol=2e-6)
+        else:
+            assert r["margin"] < 2e-5
+
+
+def test_cpu_stages_hand_example(golden_dir):
+    import json
+    g = json.load(open(os.path.join(golden_dir, "stages_example.json")))
+    X = np.array(g["points"], dtype=np.float32)
+    sub = oracle.padded_from_csr(*_csr(g["sub_rows"]), 2)
+    full = oracle.padded_from_csr(*_csr(g["full_rows"]), 2)
+    ids, d, cnt = pa.cpu_stages(X, sub, full, np.array([g["query"]], dtype=np.float32),
+                                np.array([g["beam"]], dtype=np.int32), g["ef_cpu"], g["k"], g["steps"], threads=1)
+    assert ids[0].tolist() == g["final_ids"]
+    np.testing.assert_allclose(d[0], g["final_dists"], rtol=1e-6)
+    assert cnt[0].tolist() == [g["refine_n_dist"], g["final_n_dist"], g["final_n_exp"], 0]
+
+
+def test_empty_batches_and_argument_errors(tiny):
+    X = tiny["X"]
+    ids, d, cnt = pa.cpu_stages(X, tiny["sub_adj"], tiny["adj"], np.zeros((0, 96), np.float32),
+                                np.zeros((0, 4), np.int32), 8, 5)
+    assert ids.shape == (0, 5)
+    with pytest.raises(pa.PilotannError) as e:
+        pa.cpu_stages(X, tiny["sub_adj"], tiny["adj"], tiny["Q"][:2], np.zeros((2, 4), np.int32), 0, 5)
+    assert e.value.status == -1
+    with pytest.raises(pa.PilotannError):
+        pa.build_entries(np.zeros((10, 4), np.float32), 3, [0, 1, 2])  # 10 % 3 != 0
+    with pytest.raises(pa.PilotannError) as e:
+        pa.build_entries(np.full((4, 2), np.nan, np.float32), 2, [0, 1])
+    assert e.value.status == -6

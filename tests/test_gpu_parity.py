@@ -1,0 +1,299 @@
+"""GPU parity: every stage-isolated entry point against the oracle on the same
+seeded inputs (the 10K x 96 workload: several tiles, a ragged tail), plus edge
+cases.  Tolerances (from the fp32 arithmetic of the kernels):
+* distances: |d_gpu - d_64| <= 1e-5 * d_64 for the direct L2 form, 1e-5 *
+  (|q|^2 + |x|^2) for the expanded GEMM form, 1e-5 * |q||x| for inner product;
+* ids: the ordered list equals the oracle's on >= 99.9% of queries, and a
+  query may differ only if the oracle's near-tie margin is below 2e-5;
+* counters equal wherever the ids are equal, no near tie occurred and the
+  visited cache never reset.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2503_21206_amd as pa
+from tests.workload import build_tiny, device_tables, oracle_entries, to_bf16, to_f16
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TIE = 2e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pa.device_init(0)
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return build_tiny(device="cpu")
+
+
+def _t(a, dev, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(dev).contiguous()
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------ projection
+
+def test_projection_mfma_vs_fp64(dev, tiny):
+    say("project tiny X (10000x96 -> 32) and a ragged 37-row slice")
+    X, V = tiny["X"], tiny["V32"]
+    for rows in (X, X[:37]):
+        Y = pa.project(_t(rows, dev), _t(V, dev), "f32").cpu().numpy()
+        ref = rows.astype(np.float64) @ V.astype(np.float64)
+        bound = 2 * 96 * 2.0 ** -24 * (np.abs(rows.astype(np.float64)) @ np.abs(V.astype(np.float64)))
+        assert (np.abs(Y - ref) <= bound + 1e-30).all()
+
+
+def test_projection_converters_bit_exact(dev, tiny):
+    say("project with f16 / bf16 outputs")
+    Xt, Vt = _t(tiny["X"][:1000], dev), _t(tiny["V32"], dev)
+    y32 = pa.project(Xt, Vt, "f32").cpu().numpy()
+    y16 = pa.project(Xt, Vt, "f16").cpu().numpy()
+    ybf = pa.project(Xt, Vt, "bf16").float().cpu().numpy()
+    assert (y16.view(np.uint16) == y32.astype(np.float16).view(np.uint16)).all()
+    assert (ybf == to_bf16(y32)).all()
+
+
+def test_gram_f64_and_fit_projection(dev, tiny):
+    say("gram_f64 on tiny X, then fit_projection")
+    X = tiny["X"]
+    G = torch.zeros((96, 96), dtype=torch.float64, device=dev)
+    cs = torch.zeros((96,), dtype=torch.float64, device=dev)
+    pa.gram_f64(_t(X[:6000], dev), G, cs, accumulate=False)
+    pa.gram_f64(_t(X[6000:], dev), G, cs, accumulate=True)
+    torch.cuda.synchronize()
+    X64 = X.astype(np.float64)
+    np.testing.assert_allclose(G.cpu().numpy(), X64.T @ X64, rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(cs.cpu().numpy(), X64.sum(0), rtol=1e-12, atol=1e-9)
+    V, w, mu = pa.fit_projection(X, 32, center=True)
+    np.testing.assert_allclose(w, tiny["evals"], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(mu, tiny["mean"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(V.T.astype(np.float64) @ V, np.eye(32), atol=2e-6)
+    # same subspace where the eigengap allows it (Davis-Kahan), and the same captured variance
+    Vo = tiny["V64"]
+    C = np.cov(X64.T, bias=True)
+    np.testing.assert_allclose(np.trace(V.T.astype(np.float64) @ C @ V), tiny["evals"][:32].sum(), rtol=1e-6)
+    gap = (tiny["evals"][31] - tiny["evals"][32]) / tiny["evals"][0]
+    if gap > 1e-6:
+        P1 = V.astype(np.float64) @ V.T
+        P2 = Vo @ Vo.T
+        assert np.linalg.norm(P1 - P2, 2) <= 1e-5 / gap
+
+
+def test_route(dev, tiny):
+    say("project_route 1000 queries to 32 centroids")
+    Q, V, cent = tiny["Q"], tiny["V32"], tiny["cent32"]
+    Qr, cl = pa.project_route(_t(Q, dev), _t(V, dev), _t(cent, dev))
+    cl = cl.cpu().numpy()
+    Qr64 = Q.astype(np.float64) @ V.astype(np.float64)
+    bad = 0
+    for i in range(Q.shape[0]):
+        c, margin = oracle.route(Qr64[i], cent.astype(np.float64))
+        if c != cl[i]:
+            assert margin < 1e-4, (i, c, cl[i], margin)
+            bad += 1
+    assert bad <= Q.shape[0] // 1000
+
+
+# ------------------------------------------------------------ entry selection
+
+def _fes_check(dev, w, E, Qr, metric="l2"):
+    EV, EVn, EVid = device_tables(w)
+    oi, od, ocl, _ = oracle_entries(w, E, Qr)
+    _, od1, _, _ = oracle_entries(w, min(E + 1, EV.shape[1]), Qr)
+    ids, d = pa.select_entries(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EVn, dev),
+                               _t(EVid, dev), E, metric)
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    pn = float(EVn.max())
+    bad = 0
+    for i in range(Qr.shape[0]):
+        scale = float((Qr[i].astype(np.float64) ** 2).sum()) + pn
+        tol = 1e-5 * scale
+        fin = oi[i] >= 0
+        if not (ids[i] == oi[i]).all():
+            gaps = np.diff(od1[i][np.isfinite(od1[i])])
+            assert gaps.size and gaps.min() < 2 * tol, (i, ids[i], oi[i])
+            bad += 1
+            continue
+        assert (np.abs(d[i][fin] - od[i][fin]) <= tol).all()
+        assert (d[i][~fin] == np.inf).all()
+    return bad
+
+
+def test_select_entries(dev, tiny):
+    say("select_entries E=8 (bucket size 8) and E=12 (padded)")
+    bad = _fes_check(dev, tiny, 8, tiny["Qr32"])
+    assert bad <= tiny["Q"].shape[0] // 1000
+    _fes_check(dev, tiny, 12, tiny["Qr32"][:100])
+    _fes_check(dev, tiny, 3, tiny["Qr32"][:5])
+
+
+# ------------------------------------------------------------ traversal
+
+def _traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cache_log2=0, expect_reset=False):
+    Qr = w["Qr32"][qidx]
+    adj = _t(w["sub_adj"].astype(np.int32), dev)
+    ids, d, cnt = pa.gpu_traverse(_t(Qr, dev), Xr_dev, adj, _t(entries[qidx].astype(np.int32), dev), ef, metric,
+                                  cache_log2)
+    torch.cuda.synchronize()
+    ids, d, cnt = ids.cpu().numpy(), d.cpu().numpy(), cnt.cpu().numpy()
+    assert (cnt[:, 3] == 0).all()
+    Xr64 = Xr_host.astype(np.float64)
+    bad = 0
+    for j, i in enumerate(qidx):
+        r = oracle.greedy_search(Qr[j], Xr64, w["sr"], w["sn"], ef, entries[i], metric)
+        k = r["ids"].size
+        ref = np.full(ef, -1)
+        ref[:k] = r["ids"]
+        if not (ids[j] == ref).all():
+            assert r["margin"] < TIE, (i, ids[j][:8], ref[:8], r["margin"])
+            bad += 1
+            continue
+        assert (ids[j][k:] == -1).all() and (d[j][k:] == np.inf).all()
+        if metric == "l2":
+            assert (np.abs(d[j][:k] - r["dists"]) <= 1e-5 * r["dists"] + 1e-30).all()
+        else:
+            qn = np.linalg.norm(Qr[j].astype(np.float64))
+            xn = np.linalg.norm(Xr64[r["ids"]], axis=1)
+            assert (np.abs(d[j][:k] - r["dists"]) <= 1e-5 * qn * xn).all()
+        if r["margin"] >= TIE:
+            assert cnt[j, 0] == r["n_exp"]
+            if cnt[j, 2] == 0:
+                assert cnt[j, 1] == r["n_dist"]
+            else:
+                assert cnt[j, 1] >= r["n_dist"]
+    if expect_reset:
+        assert (cnt[:, 2] > 0).any()
+    assert bad <= max(1, len(qidx) // 1000), bad
+    return ids, d, cnt
+
+
+def test_traverse_f32_parity(dev, tiny):
+    say("gpu_traverse f32 ef=64, 1000 queries")
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    Xr = _t(tiny["Xr32"], dev)
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 64, np.arange(tiny["Q"].shape[0]))
+
+
+def test_traverse_edge_cases(dev, tiny):
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    Xr = _t(tiny["Xr32"], dev)
+    say("gpu_traverse ef=1, ragged batches m=1 and m=3")
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 1, np.arange(200))
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 16, np.array([5]))
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 16, np.array([7, 8, 9]))
+    say("gpu_traverse ef=512 (maximum), 40 queries")
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 512, np.arange(40))
+    say("gpu_traverse tiny visited cache (forced resets) stays exact")
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, 64, np.arange(100), cache_log2=8, expect_reset=True)
+    say("gpu_traverse with -1 / out-of-range entries and an empty entry list")
+    bad = ent.copy()
+    bad[:, 0] = -1
+    bad[:, 1] = 10 ** 6
+    bad[:, 2] = -7
+    _traverse_check(dev, tiny, tiny["Xr32"], Xr, bad, 32, np.arange(50))
+    Qr = _t(tiny["Qr32"][:4], dev)
+    adj = _t(tiny["sub_adj"].astype(np.int32), dev)
+    ids, d, cnt = pa.gpu_traverse(Qr, Xr, adj, torch.empty((4, 0), dtype=torch.int32, device=dev), 8)
+    assert (ids.cpu().numpy() == -1).all() and (cnt.cpu().numpy()[:, :2] == 0).all()
+    say("gpu_traverse m=0")
+    ids, d, cnt = pa.gpu_traverse(Qr[:0], Xr, adj, torch.empty((0, 8), dtype=torch.int32, device=dev), 8)
+    assert ids.shape == (0, 8)
+    with pytest.raises(pa.PilotannError):
+        pa.gpu_traverse(Qr, Xr, adj, _t(ent[:4].astype(np.int32), dev), 513)
+
+
+def test_traverse_f16_and_bf16(dev, tiny):
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    for name, conv, tdt in (("f16", to_f16, torch.float16), ("bf16", to_bf16, torch.bfloat16)):
+        say(f"gpu_traverse {name} reduced vectors ef=64, 500 queries")
+        xh = conv(tiny["Xr32"])
+        Xr = _t(np.asarray(xh, dtype=np.float32), dev, tdt)
+        _traverse_check(dev, tiny, np.asarray(xh, dtype=np.float32), Xr, ent, 64, np.arange(500))
+
+
+def test_traverse_deterministic_and_batch_invariant(dev, tiny):
+    say("gpu_traverse twice + alone-vs-batch")
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    Xr = _t(tiny["Xr32"], dev)
+    adj = _t(tiny["sub_adj"].astype(np.int32), dev)
+    Qr = _t(tiny["Qr32"], dev)
+    E = _t(ent.astype(np.int32), dev)
+    a = [x.cpu().numpy() for x in pa.gpu_traverse(Qr, Xr, adj, E, 96)]
+    b = [x.cpu().numpy() for x in pa.gpu_traverse(Qr, Xr, adj, E, 96)]
+    for x, y in zip(a, b):
+        assert (x.view(np.uint8) == y.view(np.uint8)).all()
+    for i in (0, 17, 999):
+        s = [x.cpu().numpy() for x in pa.gpu_traverse(Qr[i:i + 1], Xr, adj, E[i:i + 1], 96)]
+        assert (s[0][0] == a[0][i]).all() and (s[1][0].view(np.uint32) == a[1][i].view(np.uint32)).all()
+
+
+def test_traverse_inner_product(dev):
+    say("gpu_traverse inner product on unit-norm anisotropic data (4000 x 64 -> 32)")
+    from synth.data import anisotropic_points
+    from synth.graph import build_graph, padded_to_csr
+    X = anisotropic_points(77, 4000, 64, 16)
+    Q = anisotropic_points(78, 200, 64, 16, stream_offset=1)
+    adj = build_graph(X, 16, device="cpu")
+    rp, nb = padded_to_csr(adj)
+    V, _, _ = oracle.fit_projection(X, 32, "ip")
+    V32 = V.astype(np.float32)
+    Xr = oracle.project(X, V32).astype(np.float32)
+    Qr = oracle.project(Q, V32).astype(np.float32)
+    ent = np.stack([np.arange(0, 4000, 500)] * 200).astype(np.int32)
+    w = dict(Qr32=Qr, sub_adj=adj, sr=rp, sn=nb)
+    _traverse_check(dev, w, Xr, _t(Xr, dev), ent, 48, np.arange(200), metric="ip")
+
+
+# ------------------------------------------------------------ full pipeline
+
+def test_index_pipeline_matches_oracle(dev, tiny):
+    say("Index: set_data, set_projection, sample, build_subgraph, build_entries, search")
+    s = tiny["spec"]
+    idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f32", r=s.r, threads=4))
+    idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+    idx.set_projection(tiny["V32"])
+    from synth import node_order
+    mask = idx.sample_nodes(node_order(s.n, s.seed), round(s.rho * s.n), s.sample_mode)
+    assert (mask == tiny["mask"]).all()
+    idx.build_subgraph(mask, tiny["sr"], tiny["sn"])
+    idx.build_entries(tiny["pivots"], tiny["init"], 10)
+    V, b, c = idx.state()
+    assert (V == tiny["V32"]).all()
+    Q = tiny["Q"]
+    ids, d, cnt, st = idx.search(Q, 10, 64, 64, with_counters=True, batch=300)
+    assert st["beam_launches"] == 4 and st["beam_ms"] > 0
+    gt, gd = oracle.exact_knn(tiny["X"], Q, 10)
+    rec = oracle.recall_at_k(ids, gt, 10)
+    # the oracle pipeline on its own inputs
+    P64 = tiny["Xr32"][tiny["pivots"]]
+    oi, od, oc = oracle.pipeline(Q[:200], tiny["X"], tiny["V32"], tiny["rp"], tiny["nb"], tiny["sr"], tiny["sn"],
+                                 tiny["Xr32"], tiny["cent32"], tiny["buckets"], P64, tiny["pivots"], k=10,
+                                 ef_gpu=64, ef_cpu=64, E=8)
+    orec = oracle.recall_at_k(oi, gt[:200], 10)
+    say(f"library recall@10 {rec:.4f}  oracle recall@10 (200 q) {orec:.4f}")
+    assert rec >= orec - 0.02
+    same = np.mean([(ids[i] == oi[i]).all() for i in range(200)])
+    assert same >= 0.97
+    # final distances are exact full fp32 distances
+    full = np.stack([oracle.delta_many(Q[i], tiny["X"][ids[i]]) for i in range(50)])
+    np.testing.assert_allclose(d[:50], full, rtol=2e-6)
+    # graceful degradation: no GPU stage = plain greedy search from the FES entries
+    ids0, _, cnt0, _ = idx.search(Q[:100], 10, 64, 64, stage_mask=2, with_counters=True)
+    assert (cnt0[:, 0] == 0).all()
+    assert oracle.recall_at_k(ids0, gt[:100], 10) >= 0.9
+    idx.close()
