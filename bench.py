@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark: QPS at recall@10 = 0.95 of the full PilotANN search on one MI355X.
+
+Workload (default ``gmm1m``): N = 1,000,000 base vectors, d = 128, fp32, a
+1,024-component Gaussian mixture; 10,000 queries; L2; k = 10; graph degree 32;
+projection to 64 dims; 25% subgraph (seed + 1-hop expansion); 4,096 pivots in 32
+buckets.  Two forms are measured on the same GPU: reduced vectors stored in
+fp32 and in fp16 (fp32 arithmetic), both followed by fp32 refinement and final
+traversal on the host.  For each form the smallest ef of the sweep reaching
+recall@10 >= 0.95 is found first (untimed), then ``--warmup`` untimed and
+``--steps`` timed searches of all queries run at that ef.  One JSON line goes
+to stdout; progress goes to stderr.
+
+Roofline: the stage-1 traversal kernel is the dominant GPU kernel.  Its
+algorithmic bytes per query are 4*d_r (query) + 4*E (entries) + 4*R per
+expansion (adjacency row) + s*d_r per distance evaluation (gathered reduced
+row, s = bytes per element) + 8*ef (list out), from the kernel's own counters;
+the launch duration comes from HIP events recorded around every launch on the
+library's stream during the timed steps.  Peak = 8 TB/s HBM.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def build_fixture(spec, device):
+    from synth import base_vectors, query_vectors, node_order, pivot_choice, kmeans_init_choice
+    from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
+    from synth.knn import exact_knn
+    t = time.time()
+    X = base_vectors(spec)
+    Q = query_vectors(spec)
+    log(f"data {X.shape} + {Q.shape} in {time.time() - t:.1f}s")
+    t = time.time()
+    adj = build_graph(X, spec.degree, device=device)
+    rp, nb = padded_to_csr(adj)
+    log(f"full graph: mean degree {(adj >= 0).sum(1).mean():.2f} in {time.time() - t:.1f}s")
+    t = time.time()
+    gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device)
+    log(f"ground truth in {time.time() - t:.1f}s")
+    return dict(X=X, Q=Q, adj=adj, rp=rp, nb=nb, gt=gt, order=node_order(spec.n, spec.seed),
+                pivot_choice=pivot_choice, kmeans_init_choice=kmeans_init_choice,
+                build_subgraph_csr=build_subgraph_csr, device=device)
+
+
+def build_index(spec, fx, xr_dtype, shared):
+    import paper_2503_21206_amd as pa
+    t = time.time()
+    idx = pa.Index(pa.IndexConfig(dim=spec.dim, d_r=spec.d_r, metric=spec.metric, xr_dtype=xr_dtype, r=spec.r))
+    idx.set_data(fx["X"], fx["rp"], fx["nb"])
+    if "V" not in shared:
+        idx.fit_projection()
+        shared["V"] = idx.projection()
+    else:
+        idx.set_projection(shared["V"])
+    n_target = round(spec.rho * spec.n)
+    mask = idx.sample_nodes(fx["order"], n_target, spec.sample_mode)
+    if "sub" not in shared:
+        ts = time.time()
+        sr, sn = fx["build_subgraph_csr"](fx["X"], mask, spec.degree, device=fx["device"])
+        shared["sub"] = (mask, sr, sn)
+        log(f"subgraph reconnected over {int(mask.sum())} nodes in {time.time() - ts:.1f}s")
+    mask, sr, sn = shared["sub"]
+    idx.build_subgraph(mask, sr, sn)
+    if "pivots" not in shared:
+        S = np.nonzero(mask)[0]
+        deg = sr[1:] - sr[:-1]
+        shared["pivots"] = fx["pivot_choice"](S[deg[S] > 0], spec.n_pivots, spec.seed)
+        shared["init"] = fx["kmeans_init_choice"](spec.n_pivots, spec.r, spec.seed)
+    idx.build_entries(shared["pivots"], shared["init"], 10)
+    log(f"index ({xr_dtype}) built in {time.time() - t:.1f}s")
+    return idx
+
+
+def recall(ids, gt, k):
+    from synth.knn import recall_at_k
+    return recall_at_k(ids, gt, k)
+
+
+def sweep(idx, spec, fx, target, efs):
+    best = None
+    curve = []
+    for ef in efs:
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef)
+        rec = recall(ids, fx["gt"], spec.k)
+        qps = fx["Q"].shape[0] / (st["wall_ms"] / 1e3)
+        curve.append({"ef": ef, "recall": round(rec, 5), "qps": round(qps, 1)})
+        log(f"  ef={ef:4d} recall@{spec.k}={rec:.4f} qps={qps:,.0f}")
+        if rec >= target:
+            best = ef
+            break
+    return best, curve
+
+
+def timed(idx, spec, fx, ef, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        idx.search(fx["Q"], spec.k, ef, ef)
+    torch.cuda.synchronize()
+    agg = None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef)
+        if agg is None:
+            agg = {k: 0.0 for k in st}
+        for k, v in st.items():
+            agg[k] += v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = recall(ids, fx["gt"], spec.k)
+    return dt, agg, rec
+
+
+def roofline(spec, agg, steps, ef, E, xr_bytes):
+    m = spec.queries * steps
+    algo = (m * (4 * spec.d_r + 4 * E + 8 * ef) + agg["n_exp1"] * 4 * spec.degree
+            + agg["n_dist1"] * xr_bytes * spec.d_r)
+    launches = agg["beam_launches"]
+    per_launch_bytes = algo / launches
+    avg_ms = agg["beam_ms"] / launches
+    achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "beam_kernel", "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(avg_ms, 4),
+            "launches": int(launches)}
+
+
+def cpu_baseline(spec, fx, shared, ef, budget_s):
+    """The oracle's full pipeline, single process, on a bounded sample of queries."""
+    import oracle
+    t = time.time()
+    X = fx["X"]
+    V, _, _ = oracle.fit_projection(X, spec.d_r, spec.metric)
+    Xr = oracle.project(X, V)
+    mask, sr, sn = shared["sub"]
+    P = Xr[shared["pivots"]]
+    buckets, cent = oracle.balanced_kmeans(P, spec.r, shared["init"])
+    log(f"oracle setup {time.time() - t:.1f}s")
+    E = min(ef, spec.n_pivots // spec.r)
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < spec.queries:
+        oracle.pipeline(fx["Q"][done:done + 1], X, V, fx["rp"], fx["nb"], sr, sn, Xr, cent, buckets, P,
+                        shared["pivots"], k=spec.k, ef_gpu=ef, ef_cpu=ef, E=E, metric=spec.metric)
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(done / dt, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {spec.queries} queries, full pipeline at ef={ef}, {dt:.1f}s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gmm1m")
+    ap.add_argument("--target", type=float, default=0.95)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="f32,f16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import paper_2503_21206_amd as pa
+    from synth import SPECS
+    pa.device_init(0)
+    spec = SPECS[args.workload]
+    fx = build_fixture(spec, "cuda")
+    shared = {}
+    forms = {}
+    for form in args.forms.split(","):
+        idx = build_index(spec, fx, form, shared)
+        log(f"sweep {form}")
+        ef, curve = sweep(idx, spec, fx, args.target, spec.ef)
+        if ef is None:
+            ef = spec.ef[-1]
+            log(f"  target recall not reached; timing at ef={ef}")
+        dt, agg, rec = timed(idx, spec, fx, ef, args.steps, args.warmup)
+        E = min(ef, spec.n_pivots // spec.r)
+        xr_bytes = 4 if form == "f32" else 2
+        qps = spec.queries * args.steps / dt
+        forms[form] = {
+            "value": round(qps, 1), "ef": ef, "recall": round(rec, 5), "ms_per_step": round(dt * 1e3 / args.steps, 3),
+            "roofline": roofline(spec, agg, args.steps, ef, E, xr_bytes),
+            "gpu_stage": {"beam_ms_per_step": round(agg["beam_ms"] / args.steps, 3),
+                          "fes_ms_per_step": round(agg["fes_ms"] / args.steps, 3),
+                          "host_wait_ms_per_step": round(agg["host_wait_ms"] / args.steps, 3),
+                          "mean_n_exp1": round(agg["n_exp1"] / (spec.queries * args.steps), 1),
+                          "mean_n_dist1": round(agg["n_dist1"] / (spec.queries * args.steps), 1),
+                          "mean_n_dist2": round(agg["n_dist2"] / (spec.queries * args.steps), 1),
+                          "mean_n_dist3": round(agg["n_dist3"] / (spec.queries * args.steps), 1),
+                          "forget_events": int(agg["n_reset1"])},
+            "curve": curve,
+        }
+        log(f"{form}: ef={ef} recall={rec:.4f} qps={qps:,.0f} roofline={forms[form]['roofline']}")
+        idx.close()
+    main_form = "f32" if "f32" in forms else next(iter(forms))
+    f = forms[main_form]
+    out = {
+        "metric": "QPS at recall@10=0.95 on 1 MI355X (FP32 form; FP16 form alongside)",
+        "value": f["value"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{spec.name}: N={spec.n} d={spec.dim} {spec.metric} k={spec.k} "
+                               f"{spec.components}-component GMM, {spec.queries} queries, degree {spec.degree}, "
+                               f"d_r={spec.d_r}, rho={spec.rho} {spec.sample_mode}, {spec.n_pivots} pivots/"
+                               f"{spec.r} buckets", "ef": f["ef"], "recall": f["recall"],
+                   "host_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))},
+        "roofline": f["roofline"],
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, fx, shared, f["ef"], args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

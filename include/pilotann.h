@@ -175,8 +175,9 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
  * entries_dev [m][E] int32 (-1 skipped; ids outside [0, N) are skipped).  Outputs:
  * ids_dev/d_dev [m][ef] - the final candidate list C in (delta, id) order, padded with
  * (-1, +inf); counters_dev [m][4] int32 = (expansions, distance evaluations,
- * visited-cache resets, 0).  The result equals Algorithm 1 with an exact visited set; the
- * distance-evaluation count equals |visited| when no reset happened; counters[i][3] is a
+ * visited-cache forget events, guard flag); a forget event is a cache reset or an id that
+ * found no free cache slot.  The result equals Algorithm 1 with an exact visited set; the
+ * distance-evaluation count equals |visited| when no forget event happened; counters[i][3] is a
  * termination-guard flag (0).  1 <= ef <= PA_MAX_EF,
  * 1 <= R <= PA_MAX_DEGREE.  cache_log2 selects the per-query LDS visited-cache size
  * (2^cache_log2 entries, 8..13; 0 = automatic).  Xr_dev must hold N rows.

@@ -407,6 +407,11 @@ class Index:
         _check(lib().pa_index_build_entries(self._h, pp, pivot_ids.shape[0], pi, iters))
         self.n_p = pivot_ids.shape[0]
 
+    def projection(self):
+        V = np.empty((self.cfg.dim, self.cfg.d_r), dtype=np.float32)
+        _check(lib().pa_index_get_state(self._h, V.ctypes.data_as(_P), None, None))
+        return V
+
     def state(self):
         r, d_r, D = self.cfg.r, self.cfg.d_r, self.cfg.dim
         V = np.empty((D, d_r), dtype=np.float32)

@@ -139,6 +139,7 @@ struct Wave {
     int size = 0;
     int n_dist = 0;
     int fill = 0;
+    int forgot = 0;
 
     __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_)
         : a(args), lane(lane_) {
@@ -214,6 +215,7 @@ struct Wave {
         bool stored;
         bool fresh = test_and_set(v, stored);
         fill += __popcll(__ballot(stored));
+        forgot += __popcll(__ballot(fresh && !stored));  // scored but not remembered
         uint64_t newmask = __ballot(fresh);
         int n_new = __popcll(newmask);
         if (n_new == 0) return INT_MAX;
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
         int32_t* c = a.counters + qi * 4;
         c[0] = n_exp;
         c[1] = w.n_dist;
-        c[2] = n_reset;
+        c[2] = n_reset + w.forgot;
         c[3] = aborted;
     }
 }

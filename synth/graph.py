@@ -179,26 +179,33 @@ def build_graph(X: np.ndarray, R: int, cand: int | None = None, *, device=None,
     full = _add_reverse(x64, fwd, R)
     adj = full.cpu().numpy()
     # rows sorted by (distance, id)
-    adj = _sort_rows(X, adj)
+    adj = _sort_rows(X, adj, dev)
     if repair:
         adj = _repair(X, adj, medoid_of(X), dev)
-        adj = _sort_rows(X, adj)
+        adj = _sort_rows(X, adj, dev)
     return adj.astype(np.int32)
 
 
-def _sort_rows(X: np.ndarray, adj: np.ndarray) -> np.ndarray:
-    x = X.astype(np.float64)
-    out = np.full_like(adj, -1)
-    step = 65536
+@torch.no_grad()
+def _sort_rows(X: np.ndarray, adj: np.ndarray, device=None) -> np.ndarray:
+    """Order every row by (distance to the row's node, id); -1 padding last."""
+    dev = pick_device(device)
+    x = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32)).to(dev).double()
+    a_all = torch.as_tensor(adj).to(dev).long()
+    out = torch.full_like(a_all, -1)
+    step = 16384
+    big = torch.iinfo(torch.int64).max
     for a in range(0, adj.shape[0], step):
-        blk = adj[a:a + step]
-        v = x[np.clip(blk, 0, None)]
+        blk = a_all[a:a + step]
+        v = x[blk.clamp(min=0)]
         d = ((v - x[a:a + step, None, :]) ** 2).sum(-1)
-        d = np.where(blk >= 0, d, np.inf)
-        key_id = np.where(blk >= 0, blk, np.iinfo(np.int64).max)
-        o = np.lexsort((key_id, d), axis=1)
-        out[a:a + step] = np.take_along_axis(blk, o, 1)
-    return out
+        d = torch.where(blk >= 0, d, torch.full_like(d, float("inf")))
+        key_id = torch.where(blk >= 0, blk, torch.full_like(blk, big))
+        o = torch.argsort(key_id, dim=1, stable=True)
+        blk, d = torch.gather(blk, 1, o), torch.gather(d, 1, o)
+        o = torch.argsort(d, dim=1, stable=True)
+        out[a:a + step] = torch.gather(blk, 1, o)
+    return out.cpu().numpy()
 
 
 def padded_to_csr(adj: np.ndarray):
