@@ -154,8 +154,10 @@ def _traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cac
     assert (cnt[:, 3] == 0).all()
     Xr64 = Xr_host.astype(np.float64)
     bad = 0
+    n = Xr_host.shape[0]
     for j, i in enumerate(qidx):
-        r = oracle.greedy_search(Qr[j], Xr64, w["sr"], w["sn"], ef, entries[i], metric)
+        ent_i = np.where((entries[i] >= 0) & (entries[i] < n), entries[i], -1)  # the kernel skips the others
+        r = oracle.greedy_search(Qr[j], Xr64, w["sr"], w["sn"], ef, ent_i, metric)
         k = r["ids"].size
         ref = np.full(ef, -1)
         ref[:k] = r["ids"]
