@@ -128,30 +128,35 @@ def _append(adj: np.ndarray, u: int, v: int) -> bool:
 
 
 def _repair(X: np.ndarray, adj: np.ndarray, medoid: int, device) -> np.ndarray:
+    """Link one node of every source strongly connected component of the unreached part
+    from its nearest reached node (with a free slot); repeat until all are reached."""
     n, R = adj.shape
-    for _ in range(64):
+    for _ in range(16):
         reached = _reached_from(adj, medoid)
         if reached.all():
             return adj
-        # one representative per weakly connected piece of the unreached part
-        sub = np.nonzero(~reached)[0]
-        ncomp, lab = connected_components(_csr(adj, n), directed=True, connection="weak")
-        reps = []
-        seen = set()
-        for v in sub:
-            if lab[v] not in seen:
-                seen.add(lab[v])
-                reps.append(int(v))
-        if len(reps) == 0:
-            reps = [int(sub[0])]
+        un = np.nonzero(~reached)[0]
+        pos = np.full(n, -1, dtype=np.int64)
+        pos[un] = np.arange(un.size)
+        rows = adj[un]
+        valid = (rows >= 0) & ~reached[np.clip(rows, 0, None)]
+        src = np.repeat(np.arange(un.size), R)[valid.ravel()]
+        dst = pos[rows[valid]]
+        g = csr_matrix((np.ones(src.size, dtype=np.int8), (src, dst)), shape=(un.size, un.size))
+        ncomp, lab = connected_components(g, directed=True, connection="strong")
+        has_in = np.zeros(ncomp, dtype=bool)
+        cross = lab[src] != lab[dst]
+        has_in[lab[dst[cross]]] = True
+        _, first = np.unique(lab, return_index=True)  # smallest member of every component
+        reps = un[first[~has_in]]
         host_ok = reached & (adj < 0).any(1)
         if not host_ok.any():
             host_ok = reached
         near, _ = exact_knn(X, X[reps], 1, "l2", device=device, candidate_mask=host_ok)
-        for u, h in zip(reps, near[:, 0].tolist()):
-            if not _append(adj, int(h), u):
+        for u, h in zip(reps.tolist(), near[:, 0].tolist()):
+            if not _append(adj, int(h), int(u)):
                 adj[int(h), -1] = u
-            _append(adj, u, int(h))
+            _append(adj, int(u), int(h))
     if not _reached_from(adj, medoid).all():
         raise RuntimeError("connectivity repair did not converge")
     return adj
