@@ -14,6 +14,7 @@ from .data import (  # noqa: F401
     SPECS,
     make_rng,
     gmm_centers,
+    nested_centers,
     gmm_points,
     anisotropic_points,
     base_vectors,

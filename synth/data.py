@@ -11,7 +11,12 @@ Generator recipe (the same on every machine, independent of memory size):
   +6 spectral basis.
 
 Gaussian mixtures (the 96/128-dim workloads): ``K`` equally likely components,
-centres ~ N(0, 4 I), points = centre + N(0, I).  Anisotropic mixtures (the
+points = centre + N(0, I).  Flat mixtures (the 10K workload) draw centres
+~ N(0, 4 I).  Nested mixtures (the 1M and 100M workloads) draw the same number of
+leaf centres through a tree: level-1 centres ~ N(0, s1^2 I), each child =
+parent + N(0, s_l^2 I), with branching ``levels`` and spreads ``spreads``; this
+gives the multi-scale cluster structure of real embedding sets, where a flat
+mixture of well separated blobs has no coarse structure at all.  Anisotropic mixtures (the
 768-dim inner-product workloads): a seeded orthonormal basis ``B`` (QR of a
 Gaussian matrix, signs fixed so diag(R) > 0) and a power-law spectrum
 ``lambda_i = 1 / i``; centres ``2 B diag(sqrt(lambda)) z``, points
@@ -47,7 +52,9 @@ class WorkloadSpec:
     sample_mode: str  # "uniform" | "seed_expand"
     n_pivots: int
     ef: tuple
-    kind: str = "gmm"  # "gmm" | "aniso"
+    kind: str = "gmm"  # "gmm" (flat) | "hgmm" (nested) | "aniso"
+    levels: tuple = ()
+    spreads: tuple = ()
     r: int = 32
     xr_dtypes: tuple = ("f32",)
     extra: dict = field(default_factory=dict)
@@ -66,7 +73,8 @@ SPECS = {
         name="gmm1m", config=2, n=1_000_000, dim=128, components=1024,
         queries=10_000, metric="l2", k=10, degree=32, d_r=64, rho=0.25,
         sample_mode="seed_expand", n_pivots=4096,
-        ef=(32, 48, 64, 96, 128, 192, 256, 384, 512), xr_dtypes=("f32", "f16")),
+        ef=(32, 48, 64, 96, 128, 192, 256, 384, 512), xr_dtypes=("f32", "f16"),
+        kind="hgmm", levels=(8, 8, 16), spreads=(2.0, 1.0, 0.5)),
     "aniso10m": WorkloadSpec(
         name="aniso10m", config=3, n=10_000_000, dim=768, components=1024,
         queries=10_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
@@ -76,7 +84,7 @@ SPECS = {
         name="gmm100m", config=4, n=100_000_000, dim=96, components=16_384,
         queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
         sample_mode="seed_expand", n_pivots=16_384, ef=(64, 128, 256, 512),
-        xr_dtypes=("f16",)),
+        xr_dtypes=("f16",), kind="hgmm", levels=(16, 16, 64), spreads=(2.0, 1.0, 0.5)),
     "serve20m": WorkloadSpec(
         name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
         queries=100_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
@@ -94,6 +102,16 @@ def gmm_centers(seed: int, components: int, dim: int) -> np.ndarray:
     """Mixture centres ~ N(0, 4 I) as float64 [components][dim]."""
     rng = make_rng(seed, 0x7FFF_FFFF)
     return 2.0 * rng.standard_normal((components, dim))
+
+
+def nested_centers(seed: int, levels, spreads, dim: int) -> np.ndarray:
+    """Leaf centres of a nested mixture, float64 [prod(levels)][dim]."""
+    rng = make_rng(seed, 0x7FFF_FFFD)
+    cur = np.zeros((1, dim))
+    for branch, spread in zip(levels, spreads):
+        kids = cur[:, None, :] + spread * rng.standard_normal((cur.shape[0], branch, dim))
+        cur = kids.reshape(-1, dim)
+    return cur
 
 
 def _basis(seed: int, dim: int) -> np.ndarray:
@@ -120,7 +138,7 @@ def _chunk_rows(seed: int, stream_seed: int, chunk: int, n_rows: int, components
     rng = make_rng(stream_seed, chunk)
     comp = rng.integers(0, components, size=n_rows)
     eps = rng.standard_normal((n_rows, dim))
-    if kind == "gmm":
+    if kind in ("gmm", "hgmm"):
         x = model[comp] + eps
     else:
         centres, scale = model
@@ -132,6 +150,10 @@ def _chunk_rows(seed: int, stream_seed: int, chunk: int, n_rows: int, components
 def _rows(spec: WorkloadSpec, stream_seed: int, total: int, start: int, stop: int) -> np.ndarray:
     if spec.kind == "gmm":
         model = gmm_centers(spec.seed, spec.components, spec.dim)
+    elif spec.kind == "hgmm":
+        model = nested_centers(spec.seed, spec.levels, spec.spreads, spec.dim)
+        if model.shape[0] != spec.components:
+            raise ValueError("nested levels must multiply to the component count")
     else:
         model = _aniso_model(spec.seed, spec.components, spec.dim)
     start, stop = max(0, start), min(total, stop)
