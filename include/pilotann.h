@@ -286,7 +286,8 @@ typedef struct {
     int32_t stage_mask;   /* bit 0 GPU stage, bit 1 refinement (0: both)           */
     int32_t cache_log2;   /* GPU visited-cache size (0: automatic)                 */
     int32_t threads;      /* host threads (0: index default)                       */
-    int32_t reserved;
+    int32_t handoff;      /* stage-1 candidates handed to stage 2 per query, the
+                             best by reduced distance (0: all ef_gpu)               */
 } pa_search_opts;
 
 typedef struct {

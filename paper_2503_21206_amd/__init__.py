@@ -43,7 +43,7 @@ class Params(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("ef_gpu", C.c_int32), ("ef_cpu", C.c_int32), ("E", C.c_int32), ("batch", C.c_int32),
                 ("stage_mask", C.c_int32), ("cache_log2", C.c_int32), ("threads", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("handoff", C.c_int32)]
 
 
 class SearchStats(C.Structure):
@@ -427,7 +427,7 @@ class Index:
         return {n: (p.value or 0) for n, p in zip(names, ptrs)}
 
     def search(self, Q, k: int, ef_gpu: int, ef_cpu: int = 0, E: int = 0, batch: int = 0, stage_mask: int = 0,
-               cache_log2: int = 0, threads: int = 0, with_counters: bool = False):
+               cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0):
         Q, pq = _host(Q, np.float32)
         m = Q.shape[0]
         if Q.ndim != 2 or Q.shape[1] != self.cfg.dim:
@@ -435,7 +435,7 @@ class Index:
         ids = np.empty((m, k), dtype=np.int64)
         dist = np.empty((m, k), dtype=np.float32)
         cnt = np.empty((m, 8), dtype=np.int32) if with_counters else None
-        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, 0)
+        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff)
         st = SearchStats()
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))

@@ -52,8 +52,6 @@ public:
         mark_[v] = epoch_;
         return false;
     }
-    bool test(int32_t v) const { return mark_[v] == epoch_; }
-    void set(int32_t v) { mark_[v] = epoch_; }
 
 private:
     std::vector<uint32_t> mark_;

@@ -208,6 +208,9 @@ inline int offer(std::vector<Cand>& C, int ef, float d, int32_t v) {
 }
 
 // Algorithm 1 loop steps on graph g until no unchecked entry or max_steps (<0: no limit).
+// Memory-level parallelism: the rows of all fresh neighbours are prefetched before any of
+// them is scored, and the adjacency row of the next unchecked candidate is prefetched
+// while the current one is processed (a guess: an insertion may still precede it).
 int run_steps(const StageContext& ctx, const HostGraph& g, const float* q, int ef, int max_steps,
               Visited& vis, std::vector<Cand>& C, int32_t& n_dist) {
     int steps = 0;
@@ -221,6 +224,9 @@ int run_steps(const StageContext& ctx, const HostGraph& g, const float* q, int e
         lb = pos + 1;
         const int32_t u = C[pos].id;
         ++steps;
+        size_t nxt = pos + 1;
+        while (nxt < C.size() && C[nxt].checked) ++nxt;
+        if (nxt < C.size()) __builtin_prefetch(g.adj + static_cast<int64_t>(C[nxt].id) * g.R);
         const int32_t* row = g.adj + static_cast<int64_t>(u) * g.R;
         int nf = 0;
         for (int j = 0; j < g.R; ++j) {
@@ -233,7 +239,6 @@ int run_steps(const StageContext& ctx, const HostGraph& g, const float* q, int e
         }
         for (int j = 0; j < nf; ++j) {
             const int32_t v = fresh[j];
-            if (j + 1 < nf) prefetch_row(ctx.X + static_cast<int64_t>(fresh[j + 1]) * ctx.D, ctx.D);
             const float d = ctx.dist(q, ctx.X + static_cast<int64_t>(v) * ctx.D, ctx.D);
             ++n_dist;
             const int p = offer(C, ef, d, v);
@@ -283,12 +288,16 @@ void host_stages_one(const StageContext& ctx, const float* q, const int32_t* bea
     vis.next_epoch();
     C.clear();
     // stage 2: full distances of the handed-off candidates, re-rank, keep ef_cpu
+    // all hand-off rows are requested before the first is scored
+    constexpr int kAhead = 16;
+    for (int i = 0; i < std::min(n_beam, kAhead); ++i)
+        if (beam[i] >= 0 && beam[i] < ctx.N) prefetch_row(ctx.X + static_cast<int64_t>(beam[i]) * ctx.D, ctx.D);
     for (int i = 0; i < n_beam; ++i) {
+        if (i + kAhead < n_beam && beam[i + kAhead] >= 0 && beam[i + kAhead] < ctx.N)
+            prefetch_row(ctx.X + static_cast<int64_t>(beam[i + kAhead]) * ctx.D, ctx.D);
         const int32_t v = beam[i];
         if (v < 0 || v >= ctx.N) continue;
         if (vis.test_and_set(v)) continue;
-        if (i + 1 < n_beam && beam[i + 1] >= 0 && beam[i + 1] < ctx.N)
-            prefetch_row(ctx.X + static_cast<int64_t>(beam[i + 1]) * ctx.D, ctx.D);
         C.push_back(Cand{ctx.dist(q, ctx.X + static_cast<int64_t>(v) * ctx.D, ctx.D), v, false});
         ++cnt.dist2;
     }

@@ -177,7 +177,8 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     use_device(idx);
     ensure_pool(idx, o.threads);
     const int D = idx->p.dim, d_r = idx->p.d_r, r = idx->p.r, ef = o.ef_gpu;
-    int64_t B = o.batch > 0 ? o.batch : std::max<int64_t>(512, std::min<int64_t>(4096, (m + 7) / 8));
+    // large batches keep thousands of wavefronts resident; the host starts after the first
+    int64_t B = o.batch > 0 ? o.batch : 4096;
     B = std::min(B, m);
     const int64_t nbatch = (m + B - 1) / B;
 
@@ -234,6 +235,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     std::vector<StageCounters> sc(static_cast<size_t>(m));
     double wait_ms = 0.0;
     const int ef_cpu = o.ef_cpu;
+    const int handoff = (o.handoff > 0 && o.handoff < ef) ? o.handoff : ef;
     for (int64_t b = 0; b < nbatch; ++b) {
         const int64_t b0 = b * B, nb = std::min(B, m - b0);
         const auto w0 = std::chrono::steady_clock::now();
@@ -242,7 +244,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
         idx->pool->parallel_for(nb, [&](int64_t j, int w) {
             const int64_t i = b0 + j;
             if (gpu_stage) {
-                host_stages_one(ctx, Q + i * D, beam_pin + i * ef, ef, ef_cpu, k, refine_steps, idx->vis[w],
+                host_stages_one(ctx, Q + i * D, beam_pin + i * ef, handoff, ef_cpu, k, refine_steps, idx->vis[w],
                                 idx->lists[w], out_ids + i * k, out_d + i * k, sc[i]);
             } else {
                 host_search_one(ctx, Q + i * D, ent_pin + i * E, E, ef_cpu, k, idx->vis[w], idx->lists[w],

@@ -1,11 +1,12 @@
 // Stage 1 of PilotANN: batched greedy search (Algorithm 1) on the sampled subgraph with
 // SVD-reduced vectors (section 4.1), one 64-lane wavefront per query.
 //
-// Per wavefront, in LDS:
-//   keys[ef]   the candidate list C, sorted ascending by the 64-bit key
-//              (orderable(distance) << 32) | (id << 1) | checked
-//   stage      64-slot staging area for the current batch of neighbours
-//   cache[H]   open-addressing visited cache of node ids (linear probing, LDS CAS)
+// Per wavefront:
+//   c[CH] (VGPRs)  the candidate list C, sorted ascending by the 64-bit key
+//                  (orderable(distance) << 32) | (id << 1) | checked; entry t lives in
+//                  lane t % 64 of register t / 64; slots at or beyond |C| hold +inf
+//   LDS            a scatter area for merges, a 64-slot staging area for the current batch
+//                  of neighbours, and an open-addressing visited cache of node ids
 //
 // Exactness.  The paper keeps visited nodes in a lossy shared-memory Bloom filter
 // (section 4.3) and lets the CPU stages repair its false positives.  This kernel instead
@@ -16,15 +17,15 @@
 // the merge, and if v had left C then C was full and its ef-th key has only decreased
 // since, so v is rejected again.  Either way C evolves exactly as in Algorithm 1; only
 // the count of distance evaluations can exceed |visited| (reported per query together
-// with the number of cache resets).
+// with the number of forget events).
 //
-// One loop step: find the first unchecked entry of C, mark it checked, fetch its
-// adjacency row (one coalesced load of R ids), test-and-set the ids in the cache,
-// gather the reduced vectors of the new ids (16 bytes per lane, GS lanes per vector,
-// all loads in flight together), reduce distances across the GS lanes with a fixed
-// butterfly, drop candidates not better than C[ef-1] or already in C, and merge the
-// survivors into C by co-ranking (binary search of each survivor in C plus its rank among
-// the survivors; existing entries shift by the number of survivors placed before them).
+// One loop step: find the first unchecked entry of C (one ballot per register), mark it
+// checked, fetch its adjacency row (one coalesced load of R ids), test-and-set the ids in
+// the cache, gather the reduced vectors of the new ids (16 bytes per lane, GS lanes per
+// vector, all loads in flight together), reduce each distance across its GS lanes with
+// DPP butterflies, drop candidates not better than C[ef-1] or already in C, rank the
+// survivors against C and against each other with ballots, and apply the merge as one
+// scatter to LDS and one gather back into the registers.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -35,8 +36,8 @@ namespace pa {
 namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr int kRounds = 8;       // gather rounds kept in flight per batch
-constexpr int kMaxChunks = PA_MAX_EF / 64;
+constexpr uint64_t kInf = ~0ull;
+constexpr int kRounds = 4;  // gather rounds kept in flight per batch
 constexpr int kProbes = 16;
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
@@ -62,6 +63,28 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 __device__ __forceinline__ uint32_t hash_slot(uint32_t v, int hlog) {
     return (v * 0x9E3779B1u) >> (32 - hlog);
 }
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), l);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), l);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+// Sum over aligned groups of gs lanes.  Every lane of a group ends with the same value and
+// every group combines its lanes in the same order, so a vector's distance does not depend
+// on which group scored it.
+__device__ __forceinline__ float group_sum(float s, int gs) {
+    if (gs >= 2) s += dpp<0xB1>(s);   // quad_perm [1,0,3,2]: lane ^ 1
+    if (gs >= 4) s += dpp<0x4E>(s);   // quad_perm [2,3,0,1]: lane ^ 2
+    if (gs >= 8) s += dpp<0x141>(s);  // row_half_mirror: the other quad of the 8
+    if (gs >= 16) s += dpp<0x140>(s); // row_mirror: the other half of the 16
+    if (gs >= 32) s += __shfl_xor(s, 16);
+    if (gs >= 64) s += __shfl_xor(s, 32);
+    return s;
+}
 
 struct BeamArgs {
     const float* qr;
@@ -75,7 +98,6 @@ struct BeamArgs {
     const int32_t* entries;
     int E;
     int ef;
-    int ef_alloc;
     int hlog;
     int gs_log;  // log2 of lanes per gathered vector
     int cpr;     // 16-byte chunks per reduced row
@@ -124,16 +146,21 @@ struct Chunk<PA_BF16> {
     }
 };
 
-template <int DT, int MET>
+template <int CH>
+constexpr int wave_lds_bytes(int hlog) {
+    return CH * 64 * 8 + 64 * 8 + 64 * 4 + (4 << hlog);
+}
+
+template <int DT, int MET, int CH>
 struct Wave {
     static constexpr int EPC = Chunk<DT>::kElems;
 
     const BeamArgs& a;
     int lane, sub, grp, gs, vpl, hmask;
-    uint64_t* keys;
+    uint64_t c[CH];
+    uint64_t* tmp;
     uint64_t* st_key;
     uint32_t* st_id;
-    int32_t* st_pos;
     uint32_t* cache;
     float qv[EPC];
     int size = 0;
@@ -141,21 +168,29 @@ struct Wave {
     int fill = 0;
     int forgot = 0;
 
-    __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_)
-        : a(args), lane(lane_) {
+    __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_) : a(args), lane(lane_) {
         gs = 1 << a.gs_log;
         vpl = 64 >> a.gs_log;
         sub = lane & (gs - 1);
         grp = lane >> a.gs_log;
         hmask = (1 << a.hlog) - 1;
-        keys = reinterpret_cast<uint64_t*>(base);
-        st_key = keys + a.ef_alloc;
+        tmp = reinterpret_cast<uint64_t*>(base);
+        st_key = tmp + CH * 64;
         st_id = reinterpret_cast<uint32_t*>(st_key + 64);
-        st_pos = reinterpret_cast<int32_t*>(st_id + 64);
-        cache = reinterpret_cast<uint32_t*>(st_pos + 64);
+        cache = st_id + 64;
+#pragma unroll
+        for (int w = 0; w < CH; ++w) c[w] = kInf;
         const float* q = a.qr + qi * a.d_r;
 #pragma unroll
         for (int e = 0; e < EPC; ++e) qv[e] = (sub < a.cpr) ? q[sub * EPC + e] : 0.0f;
+    }
+
+    __device__ uint64_t key_at(int t) const {  // t uniform, t < CH * 64
+        uint64_t k = kInf;
+#pragma unroll
+        for (int w = 0; w < CH; ++w)
+            if (w == (t >> 6)) k = readlane64(c[w], t & 63);
+        return k;
     }
 
     __device__ void clear_cache() {
@@ -170,7 +205,7 @@ struct Wave {
         if (v < 0) return false;
         uint32_t h = hash_slot(static_cast<uint32_t>(v), a.hlog);
         for (int p = 0; p < kProbes; ++p) {
-            uint32_t old = atomicCAS(&cache[h], kEmpty, static_cast<uint32_t>(v));
+            const uint32_t old = atomicCAS(&cache[h], kEmpty, static_cast<uint32_t>(v));
             if (old == kEmpty) {
                 stored = true;
                 return true;
@@ -183,9 +218,10 @@ struct Wave {
 
     // Re-populate the cache with the ids currently in C after a reset.
     __device__ void reseed_cache() {
-        for (int t0 = 0; t0 < size; t0 += 64) {
-            int t = t0 + lane;
-            int v = (t < size) ? static_cast<int>(static_cast<uint32_t>(keys[t]) >> 1) : -1;
+#pragma unroll
+        for (int w = 0; w < CH; ++w) {
+            const int t = w * 64 + lane;
+            const int v = (t < size) ? static_cast<int>(static_cast<uint32_t>(c[w]) >> 1) : -1;
             bool stored;
             test_and_set(v, stored);
             fill += __popcll(__ballot(stored));
@@ -200,7 +236,7 @@ struct Wave {
 #pragma unroll
         for (int e = 0; e < EPC; ++e) {
             if (MET == PA_METRIC_L2) {
-                float d = qv[e] - x[e];
+                const float d = qv[e] - x[e];
                 s = __builtin_fmaf(d, d, s);
             } else {
                 s = __builtin_fmaf(qv[e], x[e], s);
@@ -213,11 +249,11 @@ struct Wave {
     // entry was inserted (INT_MAX if none).
     __device__ int offer(int v) {
         bool stored;
-        bool fresh = test_and_set(v, stored);
+        const bool fresh = test_and_set(v, stored);
         fill += __popcll(__ballot(stored));
         forgot += __popcll(__ballot(fresh && !stored));  // scored but not remembered
-        uint64_t newmask = __ballot(fresh);
-        int n_new = __popcll(newmask);
+        const uint64_t newmask = __ballot(fresh);
+        const int n_new = __popcll(newmask);
         if (n_new == 0) return INT_MAX;
         if (fresh) st_id[mbcnt(newmask)] = static_cast<uint32_t>(v);
         wave_sync();
@@ -228,110 +264,106 @@ struct Wave {
             uint4 raw[kRounds];
 #pragma unroll
             for (int rr = 0; rr < kRounds; ++rr) {
-                int c = b0 + rr * vpl + grp;
+                const int ci = b0 + rr * vpl + grp;
                 raw[rr] = make_uint4(0, 0, 0, 0);
-                if (c < n_new && sub < a.cpr) {
-                    const uint32_t id = st_id[c];
-                    const uint4* p = reinterpret_cast<const uint4*>(
-                        a.xr + static_cast<int64_t>(id) * a.row_bytes + static_cast<int64_t>(sub) * 16);
-                    raw[rr] = *p;
+                if (ci < n_new && sub < a.cpr) {
+                    const uint32_t id = st_id[ci];
+                    raw[rr] = *reinterpret_cast<const uint4*>(a.xr + static_cast<int64_t>(id) * a.row_bytes +
+                                                              static_cast<int64_t>(sub) * 16);
                 }
             }
 #pragma unroll
             for (int rr = 0; rr < kRounds; ++rr) {
+                if (b0 + rr * vpl >= n_new) break;
                 float s = (sub < a.cpr) ? lane_partial(raw[rr]) : 0.0f;
-                for (int off = gs >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                int c = b0 + rr * vpl + grp;
-                if (sub == 0 && c < n_new) {
-                    float d = (MET == PA_METRIC_L2) ? s : -s;
-                    st_key[c] = make_key(d, st_id[c]);
-                }
+                s = group_sum(s, gs);
+                const int ci = b0 + rr * vpl + grp;
+                if (sub == 0 && ci < n_new) st_key[ci] = make_key((MET == PA_METRIC_L2) ? s : -s, st_id[ci]);
             }
         }
         wave_sync();
 
-        // filter against the current ef-th key, de-duplicate against C, locate in C
-        uint64_t key = (lane < n_new) ? st_key[lane] : ~0ull;
-        bool cand = lane < n_new;
-        if (size == a.ef) cand = cand && key < (keys[a.ef - 1] & ~1ull);
+        // candidates in lanes [0, n_new); drop those not better than the ef-th key
+        const uint64_t key = (lane < n_new) ? st_key[lane] : kInf;
+        uint64_t cand = __ballot(lane < n_new);
+        if (size == a.ef) {
+            const uint64_t kth = key_at(a.ef - 1) & ~1ull;
+            cand = __ballot(lane < n_new && key < kth);
+        }
+        if (cand == 0) return INT_MAX;
+
+        // position of every candidate in C; candidates already in C are duplicates
         int pos = 0;
-        if (cand) {
-            int lo = 0, hi = size;
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if ((keys[mid] & ~1ull) < key) lo = mid + 1;
-                else hi = mid;
-            }
-            pos = lo;
-            if (pos < size && (keys[pos] & ~1ull) == key) cand = false;
-        }
-        uint64_t smask = __ballot(cand);
-        int n_ins = __popcll(smask);
-        if (n_ins == 0) return INT_MAX;
-        wave_sync();
-        if (cand) {
-            int s = mbcnt(smask);
-            st_key[s] = key;
-            st_pos[s] = pos;
-        }
-        wave_sync();
-        const bool mine = lane < n_ins;
-        const uint64_t skey = mine ? st_key[lane] : ~0ull;
-        const int spos = mine ? st_pos[lane] : INT_MAX;
-
-        // rank among survivors and the shift of every existing entry at or after minpos
         int minpos = INT_MAX;
-        for (int j = 0; j < n_ins; ++j) minpos = min(minpos, st_pos[j]);
-        minpos = uniform(minpos);
-        const int tail = size - minpos;
-        const int nchunks = (tail + 63) >> 6;
+        uint64_t surv = cand;
+        for (uint64_t mm = cand; mm; mm &= mm - 1) {
+            const int j = __builtin_ctzll(mm);
+            const uint64_t kj = readlane64(key, j);
+            int p = 0;
+            bool dup = false;
+#pragma unroll
+            for (int w = 0; w < CH; ++w) {
+                const uint64_t cw = c[w] & ~1ull;
+                p += __popcll(__ballot(cw < kj));
+                dup = dup || (__ballot(cw == kj) != 0);
+            }
+            if (dup) {
+                surv &= ~(1ull << j);
+            } else {
+                if (lane == j) pos = p;
+                minpos = min(minpos, p);
+            }
+        }
+        if (surv == 0) return INT_MAX;
+        const int n_ins = __popcll(surv);
+        const bool mine = (surv >> lane) & 1ull;
+
+        // rank of every survivor among the survivors; shift of every entry of C
         int rank = 0;
-        int shift[kMaxChunks];
-        int tpos[kMaxChunks];
+        int shift[CH];
 #pragma unroll
-        for (int c = 0; c < kMaxChunks; ++c) {
-            shift[c] = 0;
-            tpos[c] = minpos + c * 64 + lane;
+        for (int w = 0; w < CH; ++w) shift[w] = 0;
+        for (uint64_t mm = surv; mm; mm &= mm - 1) {
+            const int j = __builtin_ctzll(mm);
+            const uint64_t kj = readlane64(key, j);
+            rank += (kj < key) ? 1 : 0;
+#pragma unroll
+            for (int w = 0; w < CH; ++w) shift[w] += (kj < (c[w] & ~1ull)) ? 1 : 0;
         }
-        for (int j = 0; j < n_ins; ++j) {
-            const uint64_t kj = st_key[j];
-            const int pj = st_pos[j];
-            rank += (kj < skey) ? 1 : 0;
+
+        // merge: scatter old entries and survivors to their final positions, read back
 #pragma unroll
-            for (int c = 0; c < kMaxChunks; ++c) shift[c] += (pj <= tpos[c]) ? 1 : 0;
-        }
-        uint64_t old[kMaxChunks];
-#pragma unroll
-        for (int c = 0; c < kMaxChunks; ++c) {
-            old[c] = 0;
-            if (c < nchunks && tpos[c] < size) old[c] = keys[tpos[c]];
-        }
-        wave_sync();
-#pragma unroll
-        for (int c = 0; c < kMaxChunks; ++c) {
-            if (c < nchunks && tpos[c] < size) {
-                int nt = tpos[c] + shift[c];
-                if (nt < a.ef) keys[nt] = old[c];
+        for (int w = 0; w < CH; ++w) {
+            const int t = w * 64 + lane;
+            if (t < size) {
+                const int nt = t + shift[w];
+                if (nt < a.ef) tmp[nt] = c[w];
             }
         }
         if (mine) {
-            int fp = spos + rank;
-            if (fp < a.ef) keys[fp] = skey;
+            const int fp = pos + rank;
+            if (fp < a.ef) tmp[fp] = key;
         }
         wave_sync();
         size = min(size + n_ins, a.ef);
-        return minpos;
+#pragma unroll
+        for (int w = 0; w < CH; ++w) {
+            const int t = w * 64 + lane;
+            c[w] = (t < size) ? tmp[t] : kInf;
+        }
+        wave_sync();
+        return uniform(minpos);
     }
 };
 
-template <int DT, int MET>
+template <int DT, int MET, int CH>
 __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     const int64_t qi = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wid;
     if (qi >= a.m) return;
-    Wave<DT, MET> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane);
+    Wave<DT, MET, CH> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane);
     w.clear_cache();
 
     int n_exp = 0, n_reset = 0, aborted = 0;
@@ -349,14 +381,14 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
             w.reseed_cache();
             ++n_reset;
         }
+        // first unchecked entry at or after lb
         int fu = -1;
-        for (int b = lb; b < w.size; b += 64) {
-            int t = b + lane;
-            bool un = (t < w.size) && !(w.keys[t] & 1ull);
-            uint64_t mk = __ballot(un);
-            if (mk) {
-                fu = b + __builtin_ctzll(mk);
-                break;
+#pragma unroll
+        for (int wi = 0; wi < CH; ++wi) {
+            if (fu < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
+                const int t = wi * 64 + lane;
+                const uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & 1ull));
+                if (mk) fu = wi * 64 + __builtin_ctzll(mk);
             }
         }
         fu = uniform(fu);
@@ -365,10 +397,14 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
             aborted = 1;
             break;
         }
-        const uint64_t ku = w.keys[fu];
-        wave_sync();
-        if (lane == 0) w.keys[fu] = ku | 1ull;
-        wave_sync();
+        uint64_t ku = 0;
+#pragma unroll
+        for (int wi = 0; wi < CH; ++wi) {
+            if (wi == (fu >> 6)) {
+                ku = readlane64(w.c[wi], fu & 63);
+                if (lane == (fu & 63)) w.c[wi] |= 1ull;
+            }
+        }
         lb = fu + 1;
         const int u = uniform(static_cast<int>(static_cast<uint32_t>(ku) >> 1));
         ++n_exp;
@@ -377,43 +413,61 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
             v = a.adj[static_cast<int64_t>(u) * a.R + lane];
             if (v >= a.N) v = -1;
         }
-        int mp = w.offer(v);
+        const int mp = w.offer(v);
         lb = min(lb, mp);
     }
     int32_t* oi = a.out_ids + qi * a.ef;
     float* od = a.out_d + qi * a.ef;
-    for (int t = lane; t < a.ef; t += 64) {
-        if (t < w.size) {
-            uint64_t k = w.keys[t];
-            oi[t] = static_cast<int32_t>(static_cast<uint32_t>(k) >> 1);
-            od[t] = unord_f32(static_cast<uint32_t>(k >> 32));
-        } else {
-            oi[t] = -1;
-            od[t] = __builtin_huge_valf();
+#pragma unroll
+    for (int wi = 0; wi < CH; ++wi) {
+        const int t = wi * 64 + lane;
+        if (t < a.ef) {
+            if (t < w.size) {
+                oi[t] = static_cast<int32_t>(static_cast<uint32_t>(w.c[wi]) >> 1);
+                od[t] = unord_f32(static_cast<uint32_t>(w.c[wi] >> 32));
+            } else {
+                oi[t] = -1;
+                od[t] = __builtin_huge_valf();
+            }
         }
     }
     if (lane == 0) {
-        int32_t* c = a.counters + qi * 4;
-        c[0] = n_exp;
-        c[1] = w.n_dist;
-        c[2] = n_reset + w.forgot;
-        c[3] = aborted;
+        int32_t* cnt = a.counters + qi * 4;
+        cnt[0] = n_exp;
+        cnt[1] = w.n_dist;
+        cnt[2] = n_reset + w.forgot;
+        cnt[3] = aborted;
     }
 }
 
+template <int DT, int MET, int CH>
+void launch_typed(BeamArgs a, hipStream_t s) {
+    a.wave_bytes = wave_lds_bytes<CH>(a.hlog);
+    const int wpb = a.wave_bytes * 2 <= 64 * 1024 ? 2 : 1;
+    const int blocks = static_cast<int>((a.m + wpb - 1) / wpb);
+    const size_t lds = static_cast<size_t>(a.wave_bytes) * wpb;
+    hipLaunchKernelGGL((beam_kernel<DT, MET, CH>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+}
+
 template <int DT, int MET>
-void launch_typed(const BeamArgs& a, int waves_per_block, hipStream_t s) {
-    const int blocks = static_cast<int>((a.m + waves_per_block - 1) / waves_per_block);
-    const size_t lds = static_cast<size_t>(a.wave_bytes) * waves_per_block;
-    hipLaunchKernelGGL((beam_kernel<DT, MET>), dim3(blocks), dim3(64 * waves_per_block), lds, s, a);
+void launch_ch(const BeamArgs& a, hipStream_t s) {
+    const int ch = (a.ef + 63) / 64;
+    if (ch <= 1) launch_typed<DT, MET, 1>(a, s);
+    else if (ch <= 2) launch_typed<DT, MET, 2>(a, s);
+    else if (ch <= 4) launch_typed<DT, MET, 4>(a, s);
+    else launch_typed<DT, MET, 8>(a, s);
 }
 
 }  // namespace
 
 int beam_auto_cache_log2(int ef, int R) {
+    // about 2.5 distance evaluations per expansion and ~ef expansions per query: size the
+    // cache so that it stays below half full (its reset threshold) for typical queries
     (void)R;
-    int need = 32 * ef;
-    int lg = 11;
+    const int ef_alloc = (ef + 63) / 64 * 64;
+    int need = 6 * ef;
+    if (need < 4 * ef_alloc) need = 4 * ef_alloc;
+    int lg = 10;
     while ((1 << lg) < need && lg < 13) ++lg;
     return lg;
 }
@@ -434,28 +488,25 @@ void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dty
     a.entries = entries;
     a.E = E;
     a.ef = ef;
-    a.ef_alloc = (ef + 63) / 64 * 64;
     a.hlog = cache_log2 > 0 ? cache_log2 : beam_auto_cache_log2(ef, R);
     a.cpr = static_cast<int>(a.row_bytes / 16);
     int gs_log = 0;
     while ((1 << gs_log) < a.cpr) ++gs_log;
     a.gs_log = gs_log;
-    a.wave_bytes = a.ef_alloc * 8 + 64 * 8 + 64 * 4 + 64 * 4 + (4 << a.hlog);
     a.out_ids = ids;
     a.out_d = dists;
     a.counters = counters;
-    require((1 << a.hlog) >= 4 * a.ef_alloc, "visited cache must hold at least 4*ef entries");
+    require((1 << a.hlog) >= 4 * ((ef + 63) / 64 * 64), "visited cache must hold at least 4*ef entries");
     require(a.cpr >= 1 && a.cpr <= 64, "reduced row must be 16..1024 bytes");
-    const int wpb = a.wave_bytes * 2 <= 64 * 1024 ? 2 : 1;
     if (xr_dtype == PA_F32) {
-        if (metric == PA_METRIC_L2) launch_typed<PA_F32, PA_METRIC_L2>(a, wpb, s);
-        else launch_typed<PA_F32, PA_METRIC_IP>(a, wpb, s);
+        if (metric == PA_METRIC_L2) launch_ch<PA_F32, PA_METRIC_L2>(a, s);
+        else launch_ch<PA_F32, PA_METRIC_IP>(a, s);
     } else if (xr_dtype == PA_F16) {
-        if (metric == PA_METRIC_L2) launch_typed<PA_F16, PA_METRIC_L2>(a, wpb, s);
-        else launch_typed<PA_F16, PA_METRIC_IP>(a, wpb, s);
+        if (metric == PA_METRIC_L2) launch_ch<PA_F16, PA_METRIC_L2>(a, s);
+        else launch_ch<PA_F16, PA_METRIC_IP>(a, s);
     } else {
-        if (metric == PA_METRIC_L2) launch_typed<PA_BF16, PA_METRIC_L2>(a, wpb, s);
-        else launch_typed<PA_BF16, PA_METRIC_IP>(a, wpb, s);
+        if (metric == PA_METRIC_L2) launch_ch<PA_BF16, PA_METRIC_L2>(a, s);
+        else launch_ch<PA_BF16, PA_METRIC_IP>(a, s);
     }
     PA_HIP(hipGetLastError());
 }
