@@ -188,6 +188,18 @@ pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const voi
                           int32_t cache_log2, int32_t* ids_dev, float* d_dev,
                           int32_t* counters_dev, void* stream);
 
+/* Stage 1 with a list size per query, so that requests of uneven ef share one launch
+ * (used by the serving loop).  As pa_gpu_traverse, plus ef_dev [m] int32 with
+ * 1 <= ef_dev[i] <= ef_max: query i keeps a list of ef_dev[i] entries and uses the first
+ * min(E, ef_dev[i]) of its entries.  Output rows keep the stride ef_max; row i holds its
+ * ef_dev[i] entries followed by (-1, +inf).  Each row equals what pa_gpu_traverse returns
+ * for that query alone with ef = ef_dev[i] and E = min(E, ef_dev[i]). */
+pa_status pa_gpu_traverse_ragged(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
+                                 int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
+                                 const int32_t* entries_dev, int32_t E, const int32_t* ef_dev,
+                                 int32_t ef_max, int32_t metric, int32_t* ids_dev, float* d_dev,
+                                 int32_t* counters_dev, void* stream);
+
 /* ------------------------------------------- stages 2 and 3 on the host (4.1) */
 
 /* Residual refinement (stage 2) and final traversal (stage 3) for m queries, on host
@@ -314,6 +326,63 @@ typedef struct {
 pa_status pa_search(pa_index* idx, const float* Q_host, int64_t m, int32_t k,
                     const pa_search_opts* opts, int64_t* out_ids_host, float* out_d_host,
                     int32_t* counters_host, pa_search_stats* stats);
+
+/* ------------------------------------------------------------ serving loop */
+
+/* Continuous batching over an index (the serving form of the search; the paper batches
+ * and pipelines queries, section 4.2).  Requests of uneven k and ef are queued in arrival
+ * order; a scheduler admits the head of the queue into a micro-batch while the device
+ * state of all admitted, unfinished requests fits hbm_budget bytes (a request holds
+ * 4*dim + 4*d_r + 8*min(ef, n/r) + 8*ef + 24 bytes) and one of `streams` micro-batch slots is
+ * free; projection, routing, entry selection and stage 1 of a micro-batch run on its slot's
+ * stream, so several micro-batches overlap on the GPU, and stage-1 lists stay in HBM until
+ * the hand-off.  Stages 2-3 run on host threads with ef_cpu = ef.  Each request's result
+ * is the same whatever else is in flight.  The index must outlive the server and must not
+ * be rebuilt while it runs; pa_search on the same index may run concurrently. */
+typedef struct pa_server pa_server;
+
+typedef struct {
+    int64_t hbm_budget;  /* bytes of request state in flight on the device (> 0)        */
+    int32_t max_batch;   /* requests per micro-batch (0: 1024)                          */
+    int32_t streams;     /* micro-batch slots / GPU streams (0: 2)                      */
+    int32_t threads;     /* host threads for stages 2-3 (0: index default)             */
+    int32_t max_k;       /* largest k a request may ask; result rows have this width (0: 128) */
+} pa_server_params;
+
+typedef struct {
+    uint64_t tag;        /* the caller's tag                                            */
+    int32_t k, ef;       /* as submitted (ef raised to k if smaller)                     */
+    double t_submit_us;  /* monotonic microseconds since pa_server_create                */
+    double t_admit_us;   /* when its micro-batch was formed                              */
+    double t_done_us;    /* when its result was published                                */
+} pa_result_info;
+
+/* Start the scheduler and completion threads; allocates `streams` slots of max_batch
+ * requests in HBM and pinned host memory up front (none later). */
+pa_status pa_server_create(pa_index* idx, const pa_server_params* params, pa_server** out);
+
+/* Queue one query q_host [dim] fp32 (copied) with its k and ef.  Never blocks and never
+ * rejects for lack of budget: the request waits in the queue.  PA_EINVAL for k or ef out of
+ * range, PA_EHBM if the request alone exceeds the budget, PA_ESTATE after a failure. */
+pa_status pa_server_submit(pa_server* s, const float* q_host, int32_t k, int32_t ef, uint64_t tag);
+
+/* Non-blocking: move up to max_results finished requests out.  info [max_results];
+ * ids [max_results][max_k] int64 and dists [max_results][max_k] fp32, each row padded with
+ * (-1, +inf) after its k results.  *n_out receives the count.  Reports a failure of the
+ * server's threads once no result is left. */
+pa_status pa_server_poll(pa_server* s, int32_t max_results, pa_result_info* info, int64_t* ids,
+                         float* dists, int32_t* n_out);
+
+/* Block until every submitted request has finished (results stay available to poll). */
+pa_status pa_server_drain(pa_server* s);
+
+/* Counters (any pointer may be NULL): requests submitted and finished, micro-batches
+ * formed, the largest micro-batch, device bytes currently in flight. */
+pa_status pa_server_stats(const pa_server* s, int64_t* submitted, int64_t* completed, int64_t* batches,
+                          int64_t* max_batch, int64_t* bytes_in_flight);
+
+/* Drain, stop the threads and release the slots. */
+pa_status pa_server_destroy(pa_server* s);
 
 #ifdef __cplusplus
 }

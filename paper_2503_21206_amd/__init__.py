@@ -56,6 +56,16 @@ class SearchStats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32),
+                ("threads", C.c_int32), ("max_k", C.c_int32)]
+
+
+class ResultInfo(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("k", C.c_int32), ("ef", C.c_int32), ("t_submit_us", C.c_double),
+                ("t_admit_us", C.c_double), ("t_done_us", C.c_double)]
+
+
 _P = C.c_void_p
 _I32, _I64, _F64 = C.c_int32, C.c_int64, C.c_double
 
@@ -89,6 +99,13 @@ _SIGS = {
     "pa_index_device_tables": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                C.POINTER(_P), C.POINTER(_P)],
     "pa_search": [_P, _P, _I64, _I32, C.POINTER(SearchOpts), _P, _P, _P, C.POINTER(SearchStats)],
+    "pa_gpu_traverse_ragged": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P],
+    "pa_server_create": [_P, C.POINTER(ServerParams), C.POINTER(_P)],
+    "pa_server_submit": [_P, _P, _I32, _I32, C.c_uint64],
+    "pa_server_poll": [_P, _I32, C.POINTER(ResultInfo), _P, _P, C.POINTER(_I32)],
+    "pa_server_drain": [_P],
+    "pa_server_stats": [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
+    "pa_server_destroy": [_P],
 }
 
 _lib = None
@@ -297,6 +314,25 @@ def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: 
     return ids, dist, cnt
 
 
+def gpu_traverse_ragged(Qr, Xr, adj, entries, efs, metric: str = "l2", stream=None):
+    """Stage 1 with a per-query list size efs [m] (device int32) -> rows of stride max(efs)."""
+    import torch
+    m, d_r = Qr.shape
+    N, R = adj.shape
+    dt = {torch.float32: PA_F32, torch.float16: PA_F16, torch.bfloat16: PA_BF16}[Xr.dtype]
+    if tuple(Xr.shape) != (N, d_r) or entries.dim() != 2 or entries.shape[0] != m or tuple(efs.shape) != (m,):
+        raise ValueError("Xr [N][d_r], entries [m][E] and efs [m] must match Qr and adj")
+    ef_max = int(efs.max().item()) if m else 1
+    ids = torch.empty((m, ef_max), dtype=torch.int32, device=Qr.device)
+    dist = torch.empty((m, ef_max), dtype=torch.float32, device=Qr.device)
+    cnt = torch.empty((m, 4), dtype=torch.int32, device=Qr.device)
+    _check(lib().pa_gpu_traverse_ragged(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
+                                        _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"),
+                                        entries.shape[1], _dev(efs, torch.int32, "efs"), ef_max, METRICS[metric],
+                                        _dev(ids), _dev(dist), _dev(cnt), _stream(stream)))
+    return ids, dist, cnt
+
+
 def cpu_stages(X, sub_adj, full_adj, Q, beam, ef_cpu: int, k: int, refine_steps: int = 2,
                metric: str = "l2", threads: int = 0):
     X, px = _host(X, np.float32)
@@ -440,3 +476,57 @@ class Index:
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))
         return ids, dist, cnt, st.as_dict()
+
+
+class Server:
+    """Continuous-batching server over a built Index (see pa_server_* in the header)."""
+
+    def __init__(self, index: Index, hbm_budget: int, max_batch: int = 0, streams: int = 0, threads: int = 0,
+                 max_k: int = 128):
+        self.index = index
+        self.dim = index.cfg.dim
+        self.max_k = max_k
+        p = ServerParams(hbm_budget, max_batch, streams, threads, max_k)
+        h = C.c_void_p()
+        _check(lib().pa_server_create(index._h, C.byref(p), C.byref(h)))
+        self._h = h
+
+    def submit(self, q, k: int, ef: int, tag: int):
+        q, pq = _host(q, np.float32)
+        if q.shape != (self.dim,):
+            raise ValueError(f"query must be [{self.dim}]")
+        _check(lib().pa_server_submit(self._h, pq, k, ef, tag))
+
+    def poll(self, max_results: int = 4096):
+        info = (ResultInfo * max(1, max_results))()
+        ids = np.empty((max(1, max_results), self.max_k), dtype=np.int64)
+        dist = np.empty((max(1, max_results), self.max_k), dtype=np.float32)
+        n = C.c_int32(0)
+        _check(lib().pa_server_poll(self._h, max_results, info, ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
+                                    C.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = info[i]
+            out.append({"tag": r.tag, "k": r.k, "ef": r.ef, "t_submit_us": r.t_submit_us,
+                        "t_admit_us": r.t_admit_us, "t_done_us": r.t_done_us,
+                        "ids": ids[i, :r.k].copy(), "dists": dist[i, :r.k].copy()})
+        return out
+
+    def drain(self):
+        _check(lib().pa_server_drain(self._h))
+
+    def stats(self):
+        v = [C.c_int64() for _ in range(5)]
+        _check(lib().pa_server_stats(self._h, *[C.byref(x) for x in v]))
+        return dict(zip(["submitted", "completed", "batches", "max_batch", "bytes_in_flight"], [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(lib().pa_server_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -81,7 +81,8 @@ void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, i
 size_t select_entries_scratch_ints(int64_t m, int r);
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
-                 int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s);
+                 int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
+                 const int32_t* efq = nullptr);
 int beam_auto_cache_log2(int ef, int R);
 
 }  // namespace pa

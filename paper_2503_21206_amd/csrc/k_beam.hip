@@ -97,7 +97,8 @@ struct BeamArgs {
     int R;
     const int32_t* entries;
     int E;
-    int ef;
+    int ef;             // list size, and the output row stride
+    const int32_t* efq; // optional per-query list size (<= ef); entries used = min(E, efq[i])
     int hlog;
     int gs_log;  // log2 of lanes per gathered vector
     int cpr;     // 16-byte chunks per reduced row
@@ -163,12 +164,14 @@ struct Wave {
     uint32_t* st_id;
     uint32_t* cache;
     float qv[EPC];
+    int ef;
     int size = 0;
     int n_dist = 0;
     int fill = 0;
     int forgot = 0;
 
-    __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_) : a(args), lane(lane_) {
+    __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_, int ef_) : a(args), lane(lane_) {
+        ef = ef_;
         gs = 1 << a.gs_log;
         vpl = 64 >> a.gs_log;
         sub = lane & (gs - 1);
@@ -286,8 +289,8 @@ struct Wave {
         // candidates in lanes [0, n_new); drop those not better than the ef-th key
         const uint64_t key = (lane < n_new) ? st_key[lane] : kInf;
         uint64_t cand = __ballot(lane < n_new);
-        if (size == a.ef) {
-            const uint64_t kth = key_at(a.ef - 1) & ~1ull;
+        if (size == ef) {
+            const uint64_t kth = key_at(ef - 1) & ~1ull;
             cand = __ballot(lane < n_new && key < kth);
         }
         if (cand == 0) return INT_MAX;
@@ -337,15 +340,15 @@ struct Wave {
             const int t = w * 64 + lane;
             if (t < size) {
                 const int nt = t + shift[w];
-                if (nt < a.ef) tmp[nt] = c[w];
+                if (nt < ef) tmp[nt] = c[w];
             }
         }
         if (mine) {
             const int fp = pos + rank;
-            if (fp < a.ef) tmp[fp] = key;
+            if (fp < ef) tmp[fp] = key;
         }
         wave_sync();
-        size = min(size + n_ins, a.ef);
+        size = min(size + n_ins, ef);
 #pragma unroll
         for (int w = 0; w < CH; ++w) {
             const int t = w * 64 + lane;
@@ -363,13 +366,20 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
     const int wid = threadIdx.x >> 6;
     const int64_t qi = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wid;
     if (qi >= a.m) return;
-    Wave<DT, MET, CH> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane);
+    int ef = a.ef, E = a.E;
+    if (a.efq != nullptr) {
+        ef = min(max(a.efq[qi], 1), a.ef);
+        E = min(E, ef);
+    }
+    ef = uniform(ef);
+    E = uniform(E);
+    Wave<DT, MET, CH> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane, ef);
     w.clear_cache();
 
     int n_exp = 0, n_reset = 0, aborted = 0;
     const int32_t* ent = a.entries + qi * a.E;
-    for (int e0 = 0; e0 < a.E; e0 += 64) {
-        int v = (e0 + lane < a.E) ? ent[e0 + lane] : -1;
+    for (int e0 = 0; e0 < E; e0 += 64) {
+        int v = (e0 + lane < E) ? ent[e0 + lane] : -1;
         if (v < 0 || v >= a.N) v = -1;
         w.offer(v);
     }
@@ -474,9 +484,11 @@ int beam_auto_cache_log2(int ef, int R) {
 
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
-                 int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s) {
+                 int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
+                 const int32_t* efq) {
     if (m == 0) return;
     BeamArgs a{};
+    a.efq = efq;
     a.qr = Qr;
     a.m = m;
     a.d_r = d_r;
