@@ -179,6 +179,64 @@ def cpu_baseline(spec, fx, shared, ef_pair, budget_s):
                       f"ef_cpu={ef_cpu}, {dt:.1f}s"}
 
 
+def serve_bench(idx, spec, fx, rates, seconds, budget):
+    """Open-loop Poisson arrivals at each rate; latency from the scheduled arrival time.
+
+    Requests draw k from {10, 50, 100} and ef from {64, 128, 256, 512}.  The submitting
+    loop never waits for completions; latency = completion - scheduled arrival, so a
+    client that falls behind is charged to the system (no coordinated omission)."""
+    import paper_2503_21206_amd as pa
+    from synth.data import make_rng, OFF_ARRIVAL
+    out = []
+    Q = fx["Q"]
+    for rate in rates:
+        srv = pa.Server(idx, hbm_budget=budget, max_batch=1024, streams=3)
+        rng = make_rng(spec.seed + OFF_ARRIVAL, int(rate))
+        n = int(rate * seconds)
+        gaps = rng.exponential(1.0 / rate, size=n)
+        sched = np.cumsum(gaps)
+        ks = rng.choice([10, 50, 100], size=n)
+        efs = rng.choice([64, 128, 256, 512], size=n)
+        qi = rng.integers(0, Q.shape[0], size=n)
+        submit_py = np.zeros(n)
+        t0 = time.perf_counter()
+        results = []
+        i = 0
+        while i < n:
+            now = time.perf_counter() - t0
+            while i < n and sched[i] <= now:
+                submit_py[i] = time.perf_counter() - t0
+                srv.submit(Q[qi[i]], int(ks[i]), int(efs[i]), i)
+                i += 1
+            results.extend(srv.poll(4096))
+            if i < n:
+                wait = sched[i] - (time.perf_counter() - t0)
+                if wait > 2e-4:
+                    time.sleep(min(wait, 1e-3))
+        srv.drain()
+        results.extend(srv.poll(1 << 20))
+        t_end = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        by_tag = {r["tag"]: r for r in results}
+        # server clock -> python clock via each request's own submit timestamp
+        lat = []
+        hits = 0
+        for tag, r in by_tag.items():
+            offset = r["t_submit_us"] / 1e6 - submit_py[tag]
+            arrival = sched[tag] + offset
+            lat.append(r["t_done_us"] / 1e6 - arrival)
+            hits += len(set(r["ids"][:10].tolist()) & set(fx["gt"][qi[tag]][:10].tolist()))
+        lat = np.array(lat) * 1e3
+        out.append({"offered_qps": rate, "achieved_qps": round(len(by_tag) / t_end, 1),
+                    "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "recall@10": round(hits / (10 * len(by_tag)), 4), "requests": len(by_tag),
+                    "micro_batches": st["batches"], "largest_micro_batch": st["max_batch"]})
+        log(f"serve rate={rate}: {out[-1]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +247,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="f32,f16")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-budget", type=int, default=32 << 30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -205,6 +268,7 @@ def main():
     fx = build_fixture(spec, "cuda")
     shared = {}
     forms = {}
+    serving = None
     for form in args.forms.split(","):
         idx = build_index(spec, fx, form, shared)
         log(f"sweep {form}")
@@ -231,6 +295,9 @@ def main():
             "curve": curve,
         }
         log(f"{form}: ef={ef} recall={rec:.4f} qps={qps:,.0f} roofline={forms[form]['roofline']}")
+        if form == "f16" and args.serve_rates:
+            rates = [float(x) for x in args.serve_rates.split(",") if x]
+            serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
         idx.close()
     main_form = "f32" if "f32" in forms else next(iter(forms))
     f = forms[main_form]
@@ -248,9 +315,19 @@ def main():
         "roofline": f["roofline"],
         "forms": forms,
     }
+    if serving is not None:
+        out["serving"] = {"workload": f"{spec.name} index, fp16 reduced vectors; Poisson arrivals, k in "
+                                      f"{{10,50,100}}, ef in {{64,128,256,512}}, {args.serve_seconds}s per rate, "
+                                      f"HBM budget {args.serve_budget} B", "rates": serving}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, fx, shared, (f["ef_gpu"], f["ef_cpu"]), args.cpu_budget)
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
 
 
 if __name__ == "__main__":
