@@ -20,7 +20,8 @@
 // with the number of forget events).
 //
 // One loop step: find the first unchecked entry of C (one ballot per register), mark it
-// checked, fetch its adjacency row (one coalesced load of R ids), test-and-set the ids in
+// checked, take its adjacency row (one coalesced load of R ids, issued one step early for
+// the entry that was next in line when it still is), test-and-set the ids in
 // the cache, gather the reduced vectors of the new ids (16 bytes per lane, GS lanes per
 // vector, all loads in flight together), reduce each distance across its GS lanes with
 // DPP butterflies, drop candidates not better than C[ef-1] or already in C, rank the
@@ -385,43 +386,61 @@ __global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
     }
     int lb = 0;  // every position below lb holds a checked entry
     const int half = 1 << (a.hlog - 1);
+    // Speculation: the adjacency row of the unchecked entry after the one being expanded
+    // is loaded while the current step gathers and merges; the next step uses it when no
+    // insertion moved ahead of that entry, and loads the right row otherwise.
+    int spec_u = -1;
+    int spec_v = -1;
     while (true) {
         if (w.fill > half) {
             w.clear_cache();
             w.reseed_cache();
             ++n_reset;
         }
-        // first unchecked entry at or after lb
-        int fu = -1;
+        // first and second unchecked entries at or after lb
+        int fu = -1, fu2 = -1;
 #pragma unroll
         for (int wi = 0; wi < CH; ++wi) {
-            if (fu < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
+            if (fu2 < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
                 const int t = wi * 64 + lane;
-                const uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & 1ull));
-                if (mk) fu = wi * 64 + __builtin_ctzll(mk);
+                uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & 1ull));
+                if (fu < 0 && mk) {
+                    fu = wi * 64 + __builtin_ctzll(mk);
+                    mk &= mk - 1;
+                }
+                if (fu >= 0 && mk) fu2 = wi * 64 + __builtin_ctzll(mk);
             }
         }
         fu = uniform(fu);
+        fu2 = uniform(fu2);
         if (fu < 0) break;
         if (n_exp >= a.N) {  // unreachable for exact semantics (each node expands once)
             aborted = 1;
             break;
         }
-        uint64_t ku = 0;
+        uint64_t ku = 0, ku2 = 0;
 #pragma unroll
         for (int wi = 0; wi < CH; ++wi) {
             if (wi == (fu >> 6)) {
                 ku = readlane64(w.c[wi], fu & 63);
                 if (lane == (fu & 63)) w.c[wi] |= 1ull;
             }
+            if (fu2 >= 0 && wi == (fu2 >> 6)) ku2 = readlane64(w.c[wi], fu2 & 63);
         }
         lb = fu + 1;
         const int u = uniform(static_cast<int>(static_cast<uint32_t>(ku) >> 1));
         ++n_exp;
-        int v = -1;
-        if (lane < a.R) {
-            v = a.adj[static_cast<int64_t>(u) * a.R + lane];
-            if (v >= a.N) v = -1;
+        int v = spec_v;
+        if (u != spec_u) {
+            v = -1;
+            if (lane < a.R) v = a.adj[static_cast<int64_t>(u) * a.R + lane];
+        }
+        if (v >= a.N) v = -1;
+        spec_u = -1;
+        spec_v = -1;
+        if (fu2 >= 0) {
+            spec_u = uniform(static_cast<int>(static_cast<uint32_t>(ku2) >> 1));
+            if (lane < a.R) spec_v = a.adj[static_cast<int64_t>(spec_u) * a.R + lane];
         }
         const int mp = w.offer(v);
         lb = min(lb, mp);
