@@ -55,6 +55,7 @@ typedef int32_t pa_status;
 #define PA_F32 0  /* float32 */
 #define PA_F16 1  /* IEEE binary16, round-to-nearest-even from float32 */
 #define PA_BF16 2 /* bfloat16, round-to-nearest-even from float32 */
+#define PA_FP8E4M3 3 /* OCP FP8 e4m3 with a float32 scale per row (entry pivots only) */
 
 #define PA_SAMPLE_UNIFORM 0
 #define PA_SAMPLE_SEED_EXPAND 1
@@ -166,6 +167,13 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
                             int32_t d, const float* EV_dev, const float* EVnorm_dev,
                             const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
                             int32_t metric, int32_t* ids_dev, float* d_dev, void* stream);
+
+/* FP8 encoding of the entry pivots (the precision form of fast entry selection): for every
+ * row of X_host [n][d] fp32, scales_host[i] = max_j |x_ij| / 448 (1 for an all-zero row) and
+ * codes_host[i][j] = e4m3(x_ij / scales_host[i]) with round-to-nearest-even (OCP e4m3,
+ * bit-equal to torch.float8_e4m3fn on this range).  Host only. */
+pa_status pa_quantize_fp8_rows(const float* X_host, int64_t n, int32_t d, uint8_t* codes_host,
+                               float* scales_host);
 
 /* ----------------------------------------------- stage 1: GPU piloting (4.1, Alg. 1) */
 

@@ -99,6 +99,7 @@ _SIGS = {
     "pa_index_device_tables": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                C.POINTER(_P), C.POINTER(_P)],
     "pa_search": [_P, _P, _I64, _I32, C.POINTER(SearchOpts), _P, _P, _P, C.POINTER(SearchStats)],
+    "pa_quantize_fp8_rows": [_P, _I64, _I32, _P, _P],
     "pa_gpu_traverse_ragged": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P],
     "pa_server_create": [_P, C.POINTER(ServerParams), C.POINTER(_P)],
     "pa_server_submit": [_P, _P, _I32, _I32, C.c_uint64],
@@ -276,6 +277,16 @@ def build_entries(P, r: int, init, iters: int = 10):
     cent = np.empty((r, d), dtype=np.float32)
     _check(lib().pa_build_entries(pp, n_p, d, r, pi, iters, buckets.ctypes.data_as(_P), cent.ctypes.data_as(_P)))
     return buckets, cent
+
+
+def quantize_fp8_rows(X):
+    """Host FP8 e4m3 encoding with one scale per row -> (codes uint8 [n][d], scales fp32 [n])."""
+    X, px = _host(X, np.float32)
+    n, d = X.shape
+    codes = np.empty((n, d), dtype=np.uint8)
+    scales = np.empty(n, dtype=np.float32)
+    _check(lib().pa_quantize_fp8_rows(px, n, d, codes.ctypes.data_as(_P), scales.ctypes.data_as(_P)))
+    return codes, scales
 
 
 def select_entries(Qr, cluster, EV, EVnorm, EVid, E: int, metric: str = "l2", stream=None):

@@ -405,6 +405,17 @@ pa_status pa_build_entries(const float* P_host, int32_t n_p, int32_t d, int32_t 
     });
 }
 
+pa_status pa_quantize_fp8_rows(const float* X_host, int64_t n, int32_t d, uint8_t* codes_host, float* scales_host) {
+    return guarded([&] {
+        require(n >= 0 && d > 0, "need n >= 0 and d > 0");
+        if (n == 0) return;
+        require(X_host && codes_host && scales_host, "null pointer");
+        for (int64_t i = 0; i < n * d; ++i)
+            if (!std::isfinite(X_host[i])) fail(PA_ENONFINITE, "rows hold a non-finite value");
+        quantize_rows_e4m3(X_host, n, d, codes_host, scales_host);
+    });
+}
+
 pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int64_t m, int32_t d,
                             const float* EV_dev, const float* EVnorm_dev, const int32_t* EVid_dev, int32_t r,
                             int32_t n_b, int32_t E, int32_t metric, int32_t* ids_dev, float* d_dev, void* stream) {

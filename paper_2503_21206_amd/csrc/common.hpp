@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <stdexcept>
@@ -67,6 +69,45 @@ inline size_t dtype_size(int dt) {
 }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// float -> OCP FP8 e4m3 (finite range +-448, no infinities), round to nearest even.  Values
+// at or beyond 464 in magnitude have no e4m3 neighbour and map to NaN (0x7F | sign); callers
+// scale rows so that |x| <= 448.  The same bit-level rounding is used on the device.
+inline uint8_t f32_to_e4m3(float x) {
+    uint32_t b;
+    __builtin_memcpy(&b, &x, 4);
+    const uint8_t sign = static_cast<uint8_t>((b >> 24) & 0x80u);
+    const uint32_t mag = b & 0x7FFFFFFFu;
+    if (mag >= 0x43E80000u) return sign | 0x7Fu;  // >= 464 (or NaN / Inf)
+    const int e = static_cast<int>(mag >> 23) - 127;
+    if (e < -6) {  // subnormal e4m3: multiples of 2^-9
+        float a;
+        __builtin_memcpy(&a, &mag, 4);
+        const float q = __builtin_nearbyintf(a * 512.0f);  // exact scaling, RNE
+        return sign | static_cast<uint8_t>(q);           // q == 8 is the smallest normal
+    }
+    uint32_t m = mag & 0x7FFFFFu;
+    uint32_t exp8 = static_cast<uint32_t>(e + 7);
+    const uint32_t lsb = (m >> 20) & 1u;
+    m += 0x7FFFFu + lsb;
+    if (m & 0x800000u) {
+        m = 0;
+        exp8 += 1;
+    }
+    return sign | static_cast<uint8_t>((exp8 << 3) | ((m >> 20) & 7u));
+}
+
+// Per-row FP8 encoding of X [n][d]: scale_i = max|x_ij| / 448 (1 for an all-zero row),
+// code_ij = e4m3(x_ij / scale_i).
+inline void quantize_rows_e4m3(const float* X, int64_t n, int d, uint8_t* codes, float* scales) {
+    for (int64_t i = 0; i < n; ++i) {
+        float amax = 0.0f;
+        for (int j = 0; j < d; ++j) amax = std::max(amax, std::fabs(X[i * d + j]));
+        const float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        scales[i] = s;
+        for (int j = 0; j < d; ++j) codes[i * d + j] = f32_to_e4m3(X[i * d + j] / s);
+    }
+}
 
 // ---- kernel launchers (defined in the .hip translation units) ----
 

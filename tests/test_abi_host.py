@@ -219,3 +219,19 @@ def test_empty_batches_and_argument_errors(tiny):
     with pytest.raises(pa.PilotannError) as e:
         pa.build_entries(np.full((4, 2), np.nan, np.float32), 2, [0, 1])
     assert e.value.status == -6
+
+
+def test_fp8_row_encoding_matches_torch_e4m3fn():
+    import torch
+    rng = np.random.default_rng(5)
+    X = (rng.standard_normal((300, 64)) * rng.uniform(1e-6, 10, size=(300, 1))).astype(np.float32)
+    X[3] = 0.0
+    X[4, :5] = [448e-3, -1e-9, 2.5e-7, 3.0, -3.0]
+    codes, scales = pa.quantize_fp8_rows(X)
+    amax = np.abs(X).max(1)
+    np.testing.assert_array_equal(scales, np.where(amax > 0, amax / np.float32(448.0), 1.0).astype(np.float32))
+    ref = torch.tensor(X / scales[:, None]).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    np.testing.assert_array_equal(codes, ref)
+    # the largest magnitude of every non-zero row encodes to +-448
+    nz = amax > 0
+    assert (np.abs(torch.tensor(codes).view(torch.float8_e4m3fn).float().numpy()).max(1)[nz] == 448).all()
