@@ -159,9 +159,9 @@ pa_status pa_build_entries(const float* P_host, int32_t n_p, int32_t d, int32_t 
  * delta = ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP), fp32.  EV_dev [r][n_b][d] fp32
  * bucket-major pivot vectors, EVnorm_dev [r][n_b] fp32 squared norms, EVid_dev [r][n_b]
  * int32 node ids.  Outputs ids_dev [m][E] int32 and d_dev [m][E] fp32 ordered by
- * (delta, id), padded with (-1, +inf) when E > n_b.  d % 16 == 0; the 16-query tile
- * (16*d fp32 + 16*next_pow2(n_b) keys) must fit 64 KiB of LDS (n_b <= 512 at d <= 128),
- * PA_EUNSUPPORTED otherwise.
+ * (delta, id), padded with (-1, +inf) when E > n_b.  d % 16 == 0.  Buckets of up to 512
+ * pivots are scored in one pass per 16-query tile; larger buckets are scanned in chunks
+ * with a running top-E per query (same results).
  * Results of a query do not depend on the other queries of the batch. */
 pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int64_t m,
                             int32_t d, const float* EV_dev, const float* EVnorm_dev,
@@ -174,6 +174,19 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
  * bit-equal to torch.float8_e4m3fn on this range).  Host only. */
 pa_status pa_quantize_fp8_rows(const float* X_host, int64_t n, int32_t d, uint8_t* codes_host,
                                float* scales_host);
+
+/* FES in the precision form: as pa_select_entries, but each tile is scored with FP8 MFMA
+ * (v_mfma_f32_16x16x32_fp8_fp8, fp32 accumulation) on the pivots' e4m3 codes EV8_dev
+ * [r][n_b][d] uint8 with row scales EVscale_dev [r][n_b] fp32 (pa_quantize_fp8_rows) and the
+ * queries encoded the same way on the fly; the K best pivots of that approximate score
+ * (E <= K) are re-scored in fp32 from EV_dev (direct form: ||q - p||^2 or -q.p) and the best
+ * E by (fp32 distance, id) are returned.  d % 32 == 0.  PA_EUNSUPPORTED if the K-list of a
+ * 16-query tile does not fit the device's LDS. */
+pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev, int64_t m, int32_t d,
+                                const float* EV_dev, const uint8_t* EV8_dev, const float* EVscale_dev,
+                                const float* EVnorm_dev, const int32_t* EVid_dev, int32_t r, int32_t n_b,
+                                int32_t E, int32_t K, int32_t metric, int32_t* ids_dev, float* d_dev,
+                                void* stream);
 
 /* ----------------------------------------------- stage 1: GPU piloting (4.1, Alg. 1) */
 
@@ -251,6 +264,9 @@ typedef struct {
     int32_t threads;      /* host threads for stages 2-3 (<= 0: all cores)       */
     int32_t device;       /* HIP device ordinal                                  */
     int64_t hbm_budget;   /* bytes of HBM the index and search buffers may use (0 = no limit) */
+    int32_t pivot_dtype;  /* PA_F32 or PA_FP8E4M3 (precision form of entry selection)   */
+    int32_t preselect;    /* FP8 form: pivots re-scored in fp32 per query = preselect*E
+                             (0: 4), capped by the bucket size                         */
 } pa_params;
 
 /* Create an empty index.  params is copied.  *out receives the handle (library-owned;

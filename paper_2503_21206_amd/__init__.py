@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpilotann.so")
 
 PA_OK = 0
 PA_METRIC_L2, PA_METRIC_IP = 0, 1
-PA_F32, PA_F16, PA_BF16 = 0, 1, 2
+PA_F32, PA_F16, PA_BF16, PA_FP8E4M3 = 0, 1, 2, 3
 PA_SAMPLE_UNIFORM, PA_SAMPLE_SEED_EXPAND = 0, 1
 PA_MAX_EF = 512
 
@@ -37,7 +37,8 @@ class PilotannError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("d_r", C.c_int32), ("metric", C.c_int32), ("xr_dtype", C.c_int32),
                 ("r", C.c_int32), ("refine_steps", C.c_int32), ("threads", C.c_int32),
-                ("device", C.c_int32), ("hbm_budget", C.c_int64)]
+                ("device", C.c_int32), ("hbm_budget", C.c_int64), ("pivot_dtype", C.c_int32),
+                ("preselect", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
@@ -100,6 +101,7 @@ _SIGS = {
                                C.POINTER(_P), C.POINTER(_P)],
     "pa_search": [_P, _P, _I64, _I32, C.POINTER(SearchOpts), _P, _P, _P, C.POINTER(SearchStats)],
     "pa_quantize_fp8_rows": [_P, _I64, _I32, _P, _P],
+    "pa_select_entries_fp8": [_P, _P, _I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P],
     "pa_gpu_traverse_ragged": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P],
     "pa_server_create": [_P, C.POINTER(ServerParams), C.POINTER(_P)],
     "pa_server_submit": [_P, _P, _I32, _I32, C.c_uint64],
@@ -305,6 +307,25 @@ def select_entries(Qr, cluster, EV, EVnorm, EVid, E: int, metric: str = "l2", st
     return ids, dist
 
 
+def select_entries_fp8(Qr, cluster, EV, EV8, EVscale, EVnorm, EVid, E: int, K: int, metric: str = "l2",
+                       stream=None):
+    """FP8 FES: EV8 [r][n_b][d] uint8 codes and EVscale [r][n_b] fp32 row scales, fp32 EV for re-rank."""
+    import torch
+    m, d = Qr.shape
+    r, n_b = EVid.shape
+    if tuple(EV.shape) != (r, n_b, d) or tuple(EV8.shape) != (r, n_b, d) or tuple(EVscale.shape) != (r, n_b) \
+            or tuple(EVnorm.shape) != (r, n_b) or tuple(cluster.shape) != (m,):
+        raise ValueError("EV, EV8 [r][n_b][d], EVscale, EVnorm [r][n_b] and cluster [m] must match")
+    ids = torch.empty((m, E), dtype=torch.int32, device=Qr.device)
+    dist = torch.empty((m, E), dtype=torch.float32, device=Qr.device)
+    _check(lib().pa_select_entries_fp8(_dev(Qr, torch.float32, "Qr"), _dev(cluster, torch.int32, "cluster"), m, d,
+                                       _dev(EV, torch.float32, "EV"), _dev(EV8, torch.uint8, "EV8"),
+                                       _dev(EVscale, torch.float32, "EVscale"), _dev(EVnorm, torch.float32, "EVnorm"),
+                                       _dev(EVid, torch.int32, "EVid"), r, n_b, E, K, METRICS[metric], _dev(ids),
+                                       _dev(dist), _stream(stream)))
+    return ids, dist
+
+
 def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: int = 0, stream=None):
     """Stage 1 on device tensors -> (ids [m][ef] int32, dists [m][ef] fp32, counters [m][4] int32)."""
     import torch
@@ -395,6 +416,8 @@ class IndexConfig:
     threads: int = 0
     device: int = 0
     hbm_budget: int = 0
+    pivot_dtype: str = "f32"  # "f32" | "fp8"
+    preselect: int = 0
 
 
 class Index:
@@ -403,7 +426,8 @@ class Index:
     def __init__(self, cfg: IndexConfig):
         self.cfg = cfg
         p = Params(cfg.dim, cfg.d_r, METRICS[cfg.metric], DTYPES[cfg.xr_dtype], cfg.r, cfg.refine_steps,
-                   cfg.threads, cfg.device, cfg.hbm_budget)
+                   cfg.threads, cfg.device, cfg.hbm_budget, {"f32": PA_F32, "fp8": PA_FP8E4M3}[cfg.pivot_dtype],
+                   cfg.preselect)
         h = C.c_void_p()
         _check(lib().pa_index_create(C.byref(p), C.byref(h)))
         self._h = h

@@ -291,7 +291,7 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pa_abi_version(void) { return 3; }
+int32_t pa_abi_version(void) { return 4; }
 
 pa_status pa_device_init(int32_t device) {
     return guarded([&] {
@@ -431,6 +431,28 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
         PA_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), sizeof(int32_t) * select_entries_scratch_ints(m, r), s));
         launch_select_entries(Qr_dev, cluster_dev, m, d, EV_dev, EVnorm_dev, EVid_dev, r, n_b, E, metric, ids_dev,
                               d_dev, scratch, s);
+        PA_HIP(hipFreeAsync(scratch, s));
+    });
+}
+
+pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev, int64_t m, int32_t d,
+                                const float* EV_dev, const uint8_t* EV8_dev, const float* EVscale_dev,
+                                const float* EVnorm_dev, const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
+                                int32_t K, int32_t metric, int32_t* ids_dev, float* d_dev, void* stream) {
+    return guarded([&] {
+        require(m >= 0, "m must be >= 0");
+        require(d > 0 && d % 32 == 0 && d <= PA_MAX_DR, "d must be a multiple of 32 in [32, 256]");
+        require(r >= 1 && r <= 64 && n_b >= 1 && E >= 1 && E <= PA_MAX_EF && K >= E && K <= 4096,
+                "need 1<=r<=64, n_b>=1, 1<=E<=512, E<=K<=4096");
+        require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
+        if (m == 0) return;
+        require(Qr_dev && cluster_dev && EV_dev && EV8_dev && EVscale_dev && EVnorm_dev && EVid_dev && ids_dev && d_dev,
+                "null pointer");
+        hipStream_t s = as_stream(stream);
+        int32_t* scratch = nullptr;
+        PA_HIP(hipMallocAsync(reinterpret_cast<void**>(&scratch), sizeof(int32_t) * select_entries_scratch_ints(m, r), s));
+        launch_select_entries_chunked(Qr_dev, cluster_dev, m, d, EV_dev, EV8_dev, EVscale_dev, EVnorm_dev, EVid_dev, r,
+                                      n_b, E, std::min(K, n_b), metric, ids_dev, d_dev, scratch, s);
         PA_HIP(hipFreeAsync(scratch, s));
     });
 }

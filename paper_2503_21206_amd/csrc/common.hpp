@@ -120,6 +120,10 @@ void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, i
                            int E, int metric, int32_t* ids, float* dists, int32_t* scratch_i32,
                            hipStream_t s);
 size_t select_entries_scratch_ints(int64_t m, int r);
+void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
+                                   const uint8_t* EV8, const float* EVscale, const float* EVnorm,
+                                   const int32_t* EVid, int r, int n_b, int E, int K, int metric, int32_t* ids,
+                                   float* dists, int32_t* scratch_i32, hipStream_t s);
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,

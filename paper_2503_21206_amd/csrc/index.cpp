@@ -71,6 +71,29 @@ void ensure_pool(pa_index* idx, int threads) {
     }
 }
 
+}  // namespace
+
+void index_select_entries(const pa_index* idx, const float* Qr, const int32_t* cluster, int64_t m, int E,
+                          int32_t* ids, float* dists, int32_t* scratch, hipStream_t s) {
+    const int r = idx->p.r, d_r = idx->p.d_r;
+    if (idx->p.pivot_dtype == PA_FP8E4M3) {
+        const int mult = idx->p.preselect > 0 ? idx->p.preselect : 4;
+        const int K = std::min(std::max(E, mult * E), idx->n_b);
+        launch_select_entries_chunked(Qr, cluster, m, d_r, static_cast<const float*>(idx->EV_dev.p),
+                                      static_cast<const uint8_t*>(idx->EV8_dev.p),
+                                      static_cast<const float*>(idx->EVs_dev.p),
+                                      static_cast<const float*>(idx->EVn_dev.p),
+                                      static_cast<const int32_t*>(idx->EVid_dev.p), r, idx->n_b, E, std::max(K, E),
+                                      idx->p.metric, ids, dists, scratch, s);
+    } else {
+        launch_select_entries(Qr, cluster, m, d_r, static_cast<const float*>(idx->EV_dev.p),
+                              static_cast<const float*>(idx->EVn_dev.p), static_cast<const int32_t*>(idx->EVid_dev.p),
+                              r, idx->n_b, E, idx->p.metric, ids, dists, scratch, s);
+    }
+}
+
+namespace {
+
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.0f;
     PA_HIP(hipEventElapsedTime(&ms, a, b));
@@ -133,9 +156,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
         PA_HIP(hipEventRecord(ev[0], s));
         launch_project(q_dev + b0 * D, nb, D, static_cast<const float*>(idx->V_dev.p), d_r, qr_dev + b0 * d_r, PA_F32,
                        static_cast<const float*>(idx->cent_dev.p), r, cl_dev + b0, s);
-        launch_select_entries(qr_dev + b0 * d_r, cl_dev + b0, nb, d_r, static_cast<const float*>(idx->EV_dev.p),
-                              static_cast<const float*>(idx->EVn_dev.p), static_cast<const int32_t*>(idx->EVid_dev.p),
-                              r, idx->n_b, E, idx->p.metric, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev, s);
+        index_select_entries(idx, qr_dev + b0 * d_r, cl_dev + b0, nb, E, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev, s);
         PA_HIP(hipEventRecord(ev[1], s));
         if (gpu_stage) {
             launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->N,
@@ -231,6 +252,9 @@ pa_status pa_index_create(const pa_params* params, pa_index** out) {
         require((static_cast<size_t>(p.d_r) * dtype_size(p.xr_dtype)) % 16 == 0, "reduced rows must be 16-byte multiples");
         require(p.r >= 1 && p.r <= 64, "r must be in [1, 64]");
         require(p.refine_steps >= 0, "refine_steps must be >= 0");
+        require(p.pivot_dtype == PA_F32 || p.pivot_dtype == PA_FP8E4M3, "pivot_dtype must be PA_F32 or PA_FP8E4M3");
+        require(p.pivot_dtype != PA_FP8E4M3 || p.d_r % 32 == 0, "FP8 pivots need d_r % 32 == 0");
+        require(p.preselect >= 0 && p.preselect <= 64, "preselect must be in [0, 64]");
         auto idx = std::make_unique<pa_index>();
         idx->p = p;
         PA_HIP(hipSetDevice(p.device));
@@ -382,6 +406,15 @@ pa_status pa_index_build_entries(pa_index* idx, const int32_t* pivot_ids_host, i
         PA_HIP(hipMemcpy(idx->EVid_dev.p, idx->bucket_ids.data(), sizeof(int32_t) * n_p, hipMemcpyHostToDevice));
         PA_HIP(hipMemcpy(idx->cent_dev.p, idx->centroids.data(), sizeof(float) * idx->centroids.size(),
                          hipMemcpyHostToDevice));
+        if (idx->p.pivot_dtype == PA_FP8E4M3) {
+            std::vector<uint8_t> codes(EV.size());
+            std::vector<float> scales(static_cast<size_t>(n_p));
+            quantize_rows_e4m3(EV.data(), n_p, d_r, codes.data(), scales.data());
+            idx->EV8_dev.ensure(codes.size(), idx->hbm_used, idx->p.hbm_budget);
+            idx->EVs_dev.ensure(sizeof(float) * scales.size(), idx->hbm_used, idx->p.hbm_budget);
+            PA_HIP(hipMemcpy(idx->EV8_dev.p, codes.data(), codes.size(), hipMemcpyHostToDevice));
+            PA_HIP(hipMemcpy(idx->EVs_dev.p, scales.data(), sizeof(float) * scales.size(), hipMemcpyHostToDevice));
+        }
         idx->n_b = n_b;
         idx->has_entries = true;
     });

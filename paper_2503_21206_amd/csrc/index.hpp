@@ -73,7 +73,7 @@ struct pa_index {
     bool has_data = false, has_proj = false, has_sub = false, has_entries = false;
 
     int64_t hbm_used = 0;
-    pa::DevBuf V_dev, Xr_dev, adj_dev, cent_dev, EV_dev, EVn_dev, EVid_dev;
+    pa::DevBuf V_dev, Xr_dev, adj_dev, cent_dev, EV_dev, EVn_dev, EVid_dev, EV8_dev, EVs_dev;
     pa::DevBuf w_q, w_qr, w_cl, w_eid, w_ed, w_bid, w_bd, w_cnt, w_scr;
     pa::PinBuf p_q, p_beam, p_cnt, p_ent;
     hipStream_t stream = nullptr;
@@ -88,3 +88,9 @@ struct pa_index {
         if (stream) (void)hipStreamDestroy(stream);
     }
 };
+
+namespace pa {
+// Entry selection for m reduced queries with the index's tables (fp32 or FP8 form).
+void index_select_entries(const pa_index* idx, const float* Qr, const int32_t* cluster, int64_t m, int E,
+                          int32_t* ids, float* dists, int32_t* scratch, hipStream_t s);
+}  // namespace pa

@@ -8,6 +8,8 @@
 // per query taken from LDS.  The m x n distance matrix D of Algorithm 2 is never stored.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace pa {
@@ -183,9 +185,252 @@ __global__ __launch_bounds__(256) void score_kernel(const float* __restrict__ Qr
     }
 }
 
+// ---------------------------------------------------------------- chunked variant
+// Any bucket size, and the FP8 form.  The bucket is scanned in chunks of CH pivots; each
+// query row keeps its best K keys in the first K slots of an LDS work row of P (a power of
+// two >= K + CH) keys, the chunk's keys land in the next CH slots, and the owning wave
+// re-sorts the row (bitonic).  FP32 form: K = E, keys carry node ids.  FP8 form: queries
+// are encoded per row like the pivots (scale = max|q| / 448, e4m3 round to nearest even),
+// the chunk is scored with v_mfma_f32_16x16x32_fp8_fp8 into an approximate distance, the
+// best K (a multiple of E) keys carry the pivot's index in its bucket, and those K are
+// re-scored exactly in fp32 (direct form) before the top E is emitted.
+typedef long fp8x8 __attribute__((ext_vector_type(1)));
+
+__device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
+    const uint32_t b = __float_as_uint(x);
+    const uint8_t sign = static_cast<uint8_t>((b >> 24) & 0x80u);
+    const uint32_t mag = b & 0x7FFFFFFFu;
+    if (mag >= 0x43E80000u) return sign | 0x7Fu;
+    const int e = static_cast<int>(mag >> 23) - 127;
+    if (e < -6) {
+        const float q = __builtin_rintf(__uint_as_float(mag) * 512.0f);
+        return sign | static_cast<uint8_t>(q);
+    }
+    uint32_t m = mag & 0x7FFFFFu;
+    uint32_t exp8 = static_cast<uint32_t>(e + 7);
+    const uint32_t lsb = (m >> 20) & 1u;
+    m += 0x7FFFFu + lsb;
+    if (m & 0x800000u) {
+        m = 0;
+        exp8 += 1;
+    }
+    return sign | static_cast<uint8_t>((exp8 << 3) | ((m >> 20) & 7u));
+}
+
+struct FesArgs {
+    const float* Qr;
+    int d;
+    const float* EV;
+    const uint8_t* EV8;
+    const float* EVscale;
+    const float* EVnorm;
+    const int32_t* EVid;
+    int r, n_b, E, K, CH, P, metric;
+    const int32_t* scratch;
+    int32_t* out_ids;
+    float* out_d;
+};
+
+__device__ void bitonic_row(uint64_t* s, int n, int lane) {
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < n; i += 64) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t x = s[i], y = s[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+template <bool FP8>
+__global__ __launch_bounds__(256) void score_chunked_kernel(FesArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int d = a.d;
+    float* Aq = reinterpret_cast<float*>(smem);          // [kTQ][d]
+    float* qn = Aq + kTQ * d;                           // [kTQ]
+    float* qs = qn + kTQ;                               // [kTQ]
+    uint8_t* Aq8 = reinterpret_cast<uint8_t*>(qs + kTQ); // [kTQ][d]
+    uint64_t* work = reinterpret_cast<uint64_t*>(Aq8 + ((kTQ * d + 15) / 16) * 16);  // [kTQ][P]
+    __shared__ int qidx[kTQ];
+    __shared__ int s_c, s_cnt;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int r = a.r, n_b = a.n_b, K = a.K, CH = a.CH, P = a.P;
+    const int32_t* counts = a.scratch;
+    const int32_t* offsets = a.scratch + r;
+    const int32_t* tprefix = a.scratch + 2 * r + 1;
+    const int32_t* perm = a.scratch + 3 * r + 2;
+    const int b = blockIdx.x;
+    if (t == 0) {
+        int c = -1, cntq = 0;
+        if (b < tprefix[r]) {
+            c = 0;
+            while (c + 1 < r && tprefix[c + 1] <= b) ++c;
+            const int tile = b - tprefix[c];
+            const int base = offsets[c] + tile * kTQ;
+            cntq = min(kTQ, counts[c] - tile * kTQ);
+            for (int i = 0; i < kTQ; ++i) qidx[i] = (i < cntq) ? perm[base + i] : -1;
+        }
+        s_c = c;
+        s_cnt = cntq;
+    }
+    __syncthreads();
+    const int c = s_c;
+    if (c < 0) return;
+    const int cntq = s_cnt;
+    for (int idx = t; idx < kTQ * d; idx += 256) {
+        const int i = idx / d, j = idx - (idx / d) * d;
+        Aq[idx] = (i < cntq) ? a.Qr[static_cast<int64_t>(qidx[i]) * d + j] : 0.0f;
+    }
+    for (int idx = t; idx < kTQ * P; idx += 256) work[idx] = ~0ull;
+    __syncthreads();
+    if (t < kTQ) {
+        float s2 = 0.0f, amax = 0.0f;
+        for (int j = 0; j < d; ++j) {
+            const float x = Aq[t * d + j];
+            s2 = __builtin_fmaf(x, x, s2);
+            amax = fmaxf(amax, fabsf(x));
+        }
+        qn[t] = s2;
+        qs[t] = amax > 0.0f ? amax / 448.0f : 1.0f;
+    }
+    __syncthreads();
+    if (FP8) {
+        for (int idx = t; idx < kTQ * d; idx += 256) Aq8[idx] = dev_f32_to_e4m3(Aq[idx] / qs[idx / d]);
+        __syncthreads();
+    }
+
+    const int64_t cb = static_cast<int64_t>(c) * n_b;
+    const int nblk = CH / 16;
+    for (int c0 = 0; c0 < n_b; c0 += CH) {
+        for (int pb = w; pb < nblk; pb += 4) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int p = c0 + pb * 16 + (lane & 15);
+            const bool pv = p < n_b;
+            if (FP8) {
+                for (int k = 0; k < d; k += 32) {
+                    const int kk = k + 8 * (lane >> 4);
+                    long av, bv = 0;
+                    __builtin_memcpy(&av, Aq8 + (lane & 15) * d + kk, 8);
+                    if (pv) __builtin_memcpy(&bv, a.EV8 + (cb + p) * d + kk, 8);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+                }
+            } else {
+                for (int k = 0; k < d; k += 4) {
+                    const float av = Aq[(lane & 15) * d + k + (lane >> 4)];
+                    const float bv = pv ? a.EV[(cb + p) * d + k + (lane >> 4)] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 4 * (lane >> 4) + i;
+                uint64_t key = ~0ull;
+                if (pv) {
+                    const float dot = FP8 ? acc[i] * (qs[row] * a.EVscale[cb + p]) : acc[i];
+                    const float dist = (a.metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[row] + a.EVnorm[cb + p])
+                                                                  : -dot;
+                    const uint32_t low = FP8 ? static_cast<uint32_t>(p) : static_cast<uint32_t>(a.EVid[cb + p]);
+                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | low;
+                }
+                work[row * P + K + pb * 16 + (lane & 15)] = key;
+            }
+        }
+        __syncthreads();
+        for (int row = w; row < cntq; row += 4) bitonic_row(work + row * P, P, lane);
+        __syncthreads();
+        // the chunk slots are refilled by the next chunk; the tail past K + CH stays +inf
+        for (int row = w; row < cntq; row += 4)
+            for (int i = K + lane; i < K + CH; i += 64) work[row * P + i] = ~0ull;
+        __syncthreads();
+    }
+
+    for (int row = w; row < cntq; row += 4) {
+        uint64_t* s = work + row * P;
+        if (FP8) {
+            // exact fp32 re-rank of the K pre-selected pivots (direct form), keys by node id
+            for (int j = lane; j < P; j += 64) {
+                uint64_t key = ~0ull;
+                if (j < K && s[j] != ~0ull) {
+                    const int p = static_cast<int>(s[j] & 0xFFFFFFFFu);
+                    const float* pv = a.EV + (cb + p) * d;
+                    const float* qv = Aq + row * d;
+                    float acc = 0.0f;
+                    for (int k = 0; k < d; ++k) {
+                        if (a.metric == PA_METRIC_L2) {
+                            const float df = qv[k] - pv[k];
+                            acc = __builtin_fmaf(df, df, acc);
+                        } else {
+                            acc = __builtin_fmaf(qv[k], pv[k], acc);
+                        }
+                    }
+                    const float dist = (a.metric == PA_METRIC_L2) ? acc : -acc;
+                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
+                }
+                s[j] = key;
+            }
+            wave_sync();
+            bitonic_row(s, P, lane);
+        }
+        const int64_t q = qidx[row];
+        for (int e = lane; e < a.E; e += 64) {
+            int32_t id = -1;
+            float dist = __builtin_huge_valf();
+            if (e < K && s[e] != ~0ull) {
+                id = static_cast<int32_t>(s[e] & 0xFFFFFFFFu);
+                dist = unord_f32(static_cast<uint32_t>(s[e] >> 32));
+            }
+            a.out_ids[q * a.E + e] = id;
+            a.out_d[q * a.E + e] = dist;
+        }
+    }
+}
+
 }  // namespace
 
 size_t select_entries_scratch_ints(int64_t m, int r) { return static_cast<size_t>(3 * r + 2 + m); }
+
+void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
+                                   const uint8_t* EV8, const float* EVscale, const float* EVnorm,
+                                   const int32_t* EVid, int r, int n_b, int E, int K, int metric, int32_t* ids,
+                                   float* dists, int32_t* scratch_i32, hipStream_t s) {
+    if (m == 0) return;
+    require(r >= 1 && r <= kMaxClusters, "FES supports 1..64 clusters");
+    const bool fp8 = EV8 != nullptr;
+    if (fp8) require(d % 32 == 0, "FP8 entry selection needs d % 32 == 0", PA_EUNSUPPORTED);
+    if (!fp8) K = E;
+    K = std::max(K, E);
+    int dev = 0, max_lds = 64 * 1024;
+    PA_HIP(hipGetDevice(&dev));
+    PA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    auto lds_for = [&](int P) {
+        return sizeof(float) * (kTQ * d + 2 * kTQ) + static_cast<size_t>((kTQ * d + 15) / 16) * 16 +
+               sizeof(uint64_t) * static_cast<size_t>(kTQ) * P;
+    };
+    int CH = 128, P = 0;
+    for (;;) {
+        P = 1;
+        while (P < K + CH) P <<= 1;
+        if (lds_for(P) <= static_cast<size_t>(max_lds) || CH == 16) break;
+        CH >>= 1;
+    }
+    require(lds_for(P) <= static_cast<size_t>(max_lds), "FES pre-selection list does not fit in LDS", PA_EUNSUPPORTED);
+    hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
+    PA_HIP(hipGetLastError());
+    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, CH, P, metric, scratch_i32, ids, dists};
+    const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
+    if (fp8) hipLaunchKernelGGL(score_chunked_kernel<true>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
+    else hipLaunchKernelGGL(score_chunked_kernel<false>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
+    PA_HIP(hipGetLastError());
+}
 
 void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
                            const float* EVnorm, const int32_t* EVid, int r, int n_b, int E, int metric,
@@ -195,12 +440,15 @@ void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, i
     int nbp = 1;
     while (nbp < n_b) nbp <<= 1;
     if (nbp < 16) nbp = 16;
-    require(nbp <= kMaxNbPow2, "FES bucket size above 512 is not supported by this build", PA_EUNSUPPORTED);
+    if (nbp > kMaxNbPow2 || sizeof(float) * (kTQ * d + kTQ + 2) + sizeof(uint64_t) * kTQ * nbp > 64 * 1024) {
+        launch_select_entries_chunked(Qr, cluster, m, d, EV, nullptr, nullptr, EVnorm, EVid, r, n_b, E, E, metric,
+                                      ids, dists, scratch_i32, s);
+        return;
+    }
     hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
     PA_HIP(hipGetLastError());
     const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
     const size_t lds = sizeof(float) * (kTQ * d + kTQ + 2) + sizeof(uint64_t) * kTQ * nbp;
-    require(lds <= 64 * 1024, "FES tile does not fit in 64 KiB of LDS (bucket too large for d)", PA_EUNSUPPORTED);
     hipLaunchKernelGGL(score_kernel, dim3(max_tiles), dim3(256), lds, s, Qr, d, EV, EVnorm, EVid, r, n_b,
                        nbp, E, metric, scratch_i32, ids, dists);
     PA_HIP(hipGetLastError());

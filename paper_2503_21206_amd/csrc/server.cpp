@@ -121,11 +121,10 @@ void launch_slot(pa_server* s, Slot& sl) {
     PA_HIP(hipMemcpyAsync(sl.efq.p, ep, sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
     launch_project(static_cast<const float*>(sl.q.p), m, D, static_cast<const float*>(idx->V_dev.p), d_r, sl.qr.p,
                    PA_F32, static_cast<const float*>(idx->cent_dev.p), r, static_cast<int32_t*>(sl.cl.p), st);
-    launch_select_entries(static_cast<const float*>(sl.qr.p), static_cast<const int32_t*>(sl.cl.p), m, d_r,
-                          static_cast<const float*>(idx->EV_dev.p), static_cast<const float*>(idx->EVn_dev.p),
-                          static_cast<const int32_t*>(idx->EVid_dev.p), r, idx->n_b, E, idx->p.metric,
-                          static_cast<int32_t*>(sl.eid.p), static_cast<float*>(sl.ed.p),
-                          static_cast<int32_t*>(sl.scr.p), st);
+    (void)r;
+    index_select_entries(idx, static_cast<const float*>(sl.qr.p), static_cast<const int32_t*>(sl.cl.p), m, E,
+                         static_cast<int32_t*>(sl.eid.p), static_cast<float*>(sl.ed.p), static_cast<int32_t*>(sl.scr.p),
+                         st);
     launch_beam(static_cast<const float*>(sl.qr.p), m, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->N,
                 static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, static_cast<const int32_t*>(sl.eid.p), E, ef,
                 idx->p.metric, 0, static_cast<int32_t*>(sl.bid.p), static_cast<float*>(sl.bd.p),

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(L):
     for name in decl:
         assert hasattr(L, name), name
     assert decl == set(pa.symbols())
-    assert pa.abi_version() == 3
+    assert pa.abi_version() == 4
 
 
 def _csr(rows):

@@ -299,3 +299,80 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     assert (cnt0[:, 0] == 0).all()
     assert oracle.recall_at_k(ids0, gt[:100], 10) >= 0.9
     idx.close()
+
+
+# ------------------------------------------------------------ large buckets and the FP8 form
+
+def _big_bucket_tables(tiny, n_p=4096, r=2):
+    from synth import kmeans_init_choice, pivot_choice
+    S = np.nonzero(tiny["mask"])[0]
+    pivots = pivot_choice(np.arange(tiny["X"].shape[0]), n_p, 77)
+    P = tiny["Xr32"][pivots]
+    b, c = oracle.balanced_kmeans(P, r, kmeans_init_choice(n_p, r, 77), iters=3)
+    EV = P[b].astype(np.float32)
+    EVn = (EV.astype(np.float64) ** 2).sum(-1).astype(np.float32)
+    EVid = pivots[b].astype(np.int32)
+    del S
+    return P, pivots, b, c.astype(np.float32), EV, EVn, EVid
+
+
+def test_select_entries_chunked_large_bucket(dev, tiny):
+    say("select_entries with 2048-pivot buckets (chunked kernel), E=32")
+    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny)
+    Qr = tiny["Qr32"][:300]
+    oi, od, ocl, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 32)
+    _, od1, _, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 33)
+    ids, d = pa.select_entries(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EVn, dev), _t(EVid, dev),
+                               32)
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    bad = 0
+    for i in range(Qr.shape[0]):
+        tol = 1e-5 * (float((Qr[i].astype(np.float64) ** 2).sum()) + float(EVn.max()))
+        if not (ids[i] == oi[i]).all():
+            assert np.diff(od1[i]).min() < 2 * tol
+            bad += 1
+            continue
+        assert (np.abs(d[i] - od[i]) <= tol).all()
+    assert bad <= 1
+
+
+def test_select_entries_fp8_preselect_then_fp32_rerank(dev, tiny):
+    say("select_entries_fp8 with 2048-pivot buckets, E=16, K=64")
+    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny)
+    codes, scales = pa.quantize_fp8_rows(EV.reshape(-1, EV.shape[-1]))
+    EV8 = codes.reshape(EV.shape)
+    EVs = scales.reshape(EV.shape[:2])
+    Qr = tiny["Qr32"][:300]
+    oi, od, ocl, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 16)
+    ids, d = pa.select_entries_fp8(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EV8, dev),
+                                   _t(EVs, dev), _t(EVn, dev), _t(EVid, dev), 16, 64)
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    overlap = np.mean([len(set(ids[i]) & set(oi[i])) / 16 for i in range(Qr.shape[0])])
+    exact = np.mean([(ids[i] == oi[i]).all() for i in range(Qr.shape[0])])
+    say(f"fp8 pre-selection: overlap@16 {overlap:.4f}, identical lists {exact:.4f}")
+    assert overlap >= 0.99
+    # every returned distance is the exact fp32 direct-form distance of its pivot
+    Xr64 = tiny["Xr32"].astype(np.float64)
+    for i in range(Qr.shape[0]):
+        ref = ((Xr64[ids[i]] - Qr[i].astype(np.float64)) ** 2).sum(1)
+        assert (np.abs(d[i] - ref) <= 1e-5 * ref).all()
+
+
+def test_index_with_fp8_pivots(dev, tiny):
+    say("Index with fp8 pivots: search recall close to the fp32-pivot index")
+    s = tiny["spec"]
+    from synth import node_order
+    out = {}
+    for pdt in ("f32", "fp8"):
+        idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, r=s.r, threads=4, pivot_dtype=pdt))
+        idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+        idx.set_projection(tiny["V32"])
+        mask = idx.sample_nodes(node_order(s.n, s.seed), round(s.rho * s.n), s.sample_mode)
+        idx.build_subgraph(mask, tiny["sr"], tiny["sn"])
+        idx.build_entries(tiny["pivots"], tiny["init"], 10)
+        out[pdt], _, _, _ = idx.search(tiny["Q"], 10, 64, 64)
+        idx.close()
+    gt, _ = oracle.exact_knn(tiny["X"], tiny["Q"], 10)
+    r32, r8 = oracle.recall_at_k(out["f32"], gt, 10), oracle.recall_at_k(out["fp8"], gt, 10)
+    say(f"recall@10 f32 pivots {r32:.4f}, fp8 pivots {r8:.4f}")
+    assert r8 >= r32 - 0.01
