@@ -16,7 +16,7 @@ Functions without an independent pin are marked "parity unpinned" in their
 docstrings.
 """
 
-from .metric import delta, delta_many, recall_at_k  # noqa: F401
+from .metric import as_f32, delta, delta_many, recall_at_k  # noqa: F401
 from .projection import fit_projection, project  # noqa: F401
 from .knn import exact_knn  # noqa: F401
 from .sampling import sample_nodes, check_subgraph, csr_from_padded, padded_from_csr  # noqa: F401

@@ -16,6 +16,8 @@ Readings where the paper is silent:
 * ties: routing takes the lowest cluster index, entries are ordered by
   (distance, node id).
 * E (entries per query) is a parameter; the same value is given to both sides.
+* distances that decide routing and the top-E are single-precision values
+  (section 6.1): exact, then rounded once to fp32 (``precision="f64"`` keeps fp64).
 
 The bucket contents are "parity unpinned" against the paper (no worked
 example exists); they are pinned by the invariants in the tests.
@@ -25,7 +27,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .metric import delta_many
+from .metric import as_f32, delta_many
 
 
 def _sqdist(a, b) -> np.ndarray:
@@ -67,10 +69,12 @@ def balanced_kmeans(P, r: int, init_idx, iters: int = 10):
     return buckets, centroids
 
 
-def route(qr, centroids):
+def route(qr, centroids, precision: str = "f32"):
     """(nearest centroid index, relative gap to the runner-up) for one reduced query."""
     qr = np.asarray(qr, dtype=np.float64)
     d = delta_many(qr, centroids, "l2")
+    if precision == "f32":
+        d = as_f32(d)
     c = int(np.argmin(d))
     if d.shape[0] < 2:
         return c, np.inf
@@ -78,7 +82,7 @@ def route(qr, centroids):
     return c, (s[1] - s[0]) / max(abs(s[1]), 1e-300)
 
 
-def select_entries(Qr, centroids, buckets, P, pivot_ids, E: int, metric: str = "l2"):
+def select_entries(Qr, centroids, buckets, P, pivot_ids, E: int, metric: str = "l2", precision: str = "f32"):
     """Top-E pivots of the routed cluster for each query.
 
     Returns (entry ids int64 [m][E], distances fp64 [m][E], cluster int [m],
@@ -95,10 +99,12 @@ def select_entries(Qr, centroids, buckets, P, pivot_ids, E: int, metric: str = "
     clusters = np.zeros(m, dtype=np.int64)
     margins = np.full(m, np.inf)
     for i in range(m):
-        c, gap = route(Qr[i], centroids)
+        c, gap = route(Qr[i], centroids, precision)
         clusters[i] = c
         members = np.asarray(buckets[c], dtype=np.int64)
         d = delta_many(Qr[i], P[members], metric)
+        if precision == "f32":
+            d = as_f32(d)
         nid = pivot_ids[members]
         order = np.lexsort((nid, d))
         take = order[:E]

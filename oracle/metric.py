@@ -8,6 +8,11 @@
   embeddings, where both orders agree).
 * recall@k = |retrieved_k intersect groundtruth_k| / k, averaged over queries
   (section 6.1, Metrics).
+* Precision of the search: the paper computes distances in single precision
+  (section 6.1, setup).  Where a distance decides an order (Algorithm 1's list,
+  the entry top-E, routing), the oracle uses the fp32 value nearest to the exact
+  distance: computed in fp64, rounded once (``as_f32``).  The exact kNN of the
+  problem definition stays in fp64.
 """
 
 from __future__ import annotations
@@ -50,3 +55,8 @@ def recall_at_k(found, truth, k: int) -> float:
         f = [int(v) for v in f[:k] if v >= 0]
         total += len(set(f) & set(int(v) for v in t[:k]))
     return total / (k * max(1, truth.shape[0]))
+
+
+def as_f32(d):
+    """Round fp64 distances once to the nearest float32 (returned as fp64 values)."""
+    return np.asarray(d, dtype=np.float64).astype(np.float32).astype(np.float64)

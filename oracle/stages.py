@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 
 from .entries import select_entries
-from .metric import delta_many
+from .metric import as_f32, delta_many
 from .projection import project
 from .traverse import greedy_search
 
@@ -37,7 +37,7 @@ def gpu_stage(qr, Xr, sub_rowptr, sub_nbrs, entries, ef: int, metric: str = "l2"
 def refine(q, X, sub_rowptr, sub_nbrs, beam_ids, ef_cpu: int, metric: str = "l2", steps: int = 2):
     """Stage 2 for one query; returns the Algorithm 1 result dict plus total n_dist."""
     ids = [int(v) for v in beam_ids if v >= 0]
-    d = delta_many(q, X[np.asarray(ids, dtype=np.int64)], metric) if ids else np.zeros(0)
+    d = as_f32(delta_many(q, X[np.asarray(ids, dtype=np.int64)], metric)) if ids else np.zeros(0)
     res = greedy_search(q, X, sub_rowptr, sub_nbrs, ef_cpu, (), metric,
                         initial=list(zip(d.tolist(), ids)), max_steps=steps)
     res["n_dist"] += len(ids)
@@ -83,7 +83,7 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
                 c_ids, c_d, vis = r["ids"], r["dists"], r["visited"]
             else:
                 c_ids = g["ids"]
-                c_d = delta_many(Q[i], X[c_ids], metric) if c_ids.size else np.zeros(0)
+                c_d = as_f32(delta_many(Q[i], X[c_ids], metric)) if c_ids.size else np.zeros(0)
                 counters[i, 1] = c_ids.size
                 vis = set(int(v) for v in c_ids)
             ids, d, f = final_traversal(Q[i], X, rowptr, nbrs, c_ids, c_d, vis, ef_cpu, k, metric)

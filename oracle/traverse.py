@@ -12,7 +12,9 @@ Readings where the paper is silent:
   initial C is resized to ef (the first expansion is the same either way);
 * visited is an exact set, one distance per visited node, so
   n_dist = |visited| (the paper's lossy GPU filter is a separate variant);
-* expansion width is one node per loop step, as printed.
+* expansion width is one node per loop step, as printed;
+* distances are single-precision values (section 6.1): each is computed exactly
+  and rounded once to fp32 before it enters C (``precision="f64"`` keeps fp64).
 
 Inputs for the later stages: ``initial`` seeds C with already scored
 (distance, id) pairs, ``visited`` pre-populates the visited set and
@@ -30,7 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .metric import delta_many
+from .metric import as_f32, delta_many
 
 
 def _rel_gap(a: float, b: float) -> float:
@@ -45,7 +47,7 @@ def _resize_gap(sorted_keys, ef: int) -> float:
 
 
 def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "l2", *,
-                  initial=None, visited=None, max_steps=None):
+                  initial=None, visited=None, max_steps=None, precision: str = "f32"):
     """Run Algorithm 1 for one query.
 
     q        query vector (any float dtype; used in fp64)
@@ -60,6 +62,10 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
     q = np.asarray(q, dtype=np.float64)
     seen = set() if visited is None else set(int(v) for v in visited)
     n_dist = 0
+
+    def score(ids):
+        d = delta_many(q, vectors[np.asarray(ids)], metric)
+        return as_f32(d) if precision == "f32" else d
     # line 3: C <- EP
     C = []  # list of [key=(distance, id), checked]
     if initial is not None:
@@ -74,7 +80,7 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
         seen.add(e)
         fresh.append(e)
     if fresh:
-        ds = delta_many(q, vectors[np.asarray(fresh)], metric)
+        ds = score(fresh)
         n_dist += len(fresh)
         for d, v in zip(ds, fresh):
             C.append([(float(d), v), False])
@@ -101,7 +107,7 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
                 seen.add(v)
                 new.append(v)
         if new:
-            ds = delta_many(q, vectors[np.asarray(new)], metric)
+            ds = score(new)
             n_dist += len(new)
             for d, v in zip(ds, new):
                 C.append([(float(d), v), False])

@@ -38,8 +38,9 @@ private:
 
 int host_core_count();
 
-// distance between two fp32 vectors of length D (squared L2 or -dot)
-using DistFn = float (*)(const float*, const float*, int);
+// distance from a query widened to fp64 to an fp32 vector of length D (squared L2 or
+// -dot), accumulated in fp64 and rounded once to fp32
+using DistFn = float (*)(const double*, const float*, int);
 DistFn pick_distance(int metric);
 
 // Per-thread visited table: epoch-stamped marks over N nodes.

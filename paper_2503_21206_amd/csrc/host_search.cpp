@@ -92,97 +92,101 @@ int host_core_count() {
 
 namespace {
 
-float l2_scalar(const float* a, const float* b, int D) {
-    float s = 0.0f;
+// Every distance is accumulated in fp64 (the difference of two floats and its square are
+// exact there) and rounded once to fp32, so the single-precision value the search
+// compares (section 6.1) is the exact distance correctly rounded, up to the fp64 sum's
+// own ~D * 2^-53 relative error: the same value the device kernels produce, independent of
+// the summation order.  The query is widened to fp64 once per search.
+
+float l2_scalar(const double* q, const float* x, int D) {
+    double s = 0.0;
     for (int i = 0; i < D; ++i) {
-        float d = a[i] - b[i];
+        const double d = q[i] - static_cast<double>(x[i]);
         s += d * d;
     }
-    return s;
+    return static_cast<float>(s);
 }
-float ip_scalar(const float* a, const float* b, int D) {
-    float s = 0.0f;
-    for (int i = 0; i < D; ++i) s += a[i] * b[i];
-    return -s;
-}
-
-__attribute__((target("avx2,fma"))) float hsum256(__m256 v) {
-    __m128 lo = _mm256_castps256_ps128(v);
-    __m128 hi = _mm256_extractf128_ps(v, 1);
-    lo = _mm_add_ps(lo, hi);
-    __m128 sh = _mm_movehdup_ps(lo);
-    __m128 s = _mm_add_ps(lo, sh);
-    sh = _mm_movehl_ps(sh, s);
-    s = _mm_add_ss(s, sh);
-    return _mm_cvtss_f32(s);
+float ip_scalar(const double* q, const float* x, int D) {
+    double s = 0.0;
+    for (int i = 0; i < D; ++i) s += q[i] * static_cast<double>(x[i]);
+    return static_cast<float>(-s);
 }
 
-__attribute__((target("avx2,fma"))) float l2_avx2(const float* a, const float* b, int D) {
-    __m256 s0 = _mm256_setzero_ps(), s1 = _mm256_setzero_ps();
+__attribute__((target("avx2,fma"))) double hsum256d(__m256d v) {
+    __m128d lo = _mm256_castpd256_pd128(v);
+    __m128d hi = _mm256_extractf128_pd(v, 1);
+    lo = _mm_add_pd(lo, hi);
+    return _mm_cvtsd_f64(_mm_add_sd(lo, _mm_unpackhi_pd(lo, lo)));
+}
+
+__attribute__((target("avx2,fma"))) float l2_avx2(const double* q, const float* x, int D) {
+    __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+    int i = 0;
+    for (; i + 8 <= D; i += 8) {
+        __m256d d0 = _mm256_sub_pd(_mm256_loadu_pd(q + i), _mm256_cvtps_pd(_mm_loadu_ps(x + i)));
+        __m256d d1 = _mm256_sub_pd(_mm256_loadu_pd(q + i + 4), _mm256_cvtps_pd(_mm_loadu_ps(x + i + 4)));
+        s0 = _mm256_fmadd_pd(d0, d0, s0);
+        s1 = _mm256_fmadd_pd(d1, d1, s1);
+    }
+    double s = hsum256d(_mm256_add_pd(s0, s1));
+    for (; i < D; ++i) {
+        const double d = q[i] - static_cast<double>(x[i]);
+        s += d * d;
+    }
+    return static_cast<float>(s);
+}
+
+__attribute__((target("avx2,fma"))) float ip_avx2(const double* q, const float* x, int D) {
+    __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+    int i = 0;
+    for (; i + 8 <= D; i += 8) {
+        s0 = _mm256_fmadd_pd(_mm256_loadu_pd(q + i), _mm256_cvtps_pd(_mm_loadu_ps(x + i)), s0);
+        s1 = _mm256_fmadd_pd(_mm256_loadu_pd(q + i + 4), _mm256_cvtps_pd(_mm_loadu_ps(x + i + 4)), s1);
+    }
+    double s = hsum256d(_mm256_add_pd(s0, s1));
+    for (; i < D; ++i) s += q[i] * static_cast<double>(x[i]);
+    return static_cast<float>(-s);
+}
+
+__attribute__((target("avx512f"))) float l2_avx512(const double* q, const float* x, int D) {
+    __m512d s0 = _mm512_setzero_pd(), s1 = _mm512_setzero_pd();
     int i = 0;
     for (; i + 16 <= D; i += 16) {
-        __m256 d0 = _mm256_sub_ps(_mm256_loadu_ps(a + i), _mm256_loadu_ps(b + i));
-        __m256 d1 = _mm256_sub_ps(_mm256_loadu_ps(a + i + 8), _mm256_loadu_ps(b + i + 8));
-        s0 = _mm256_fmadd_ps(d0, d0, s0);
-        s1 = _mm256_fmadd_ps(d1, d1, s1);
+        __m512d d0 = _mm512_sub_pd(_mm512_loadu_pd(q + i), _mm512_cvtps_pd(_mm256_loadu_ps(x + i)));
+        __m512d d1 = _mm512_sub_pd(_mm512_loadu_pd(q + i + 8), _mm512_cvtps_pd(_mm256_loadu_ps(x + i + 8)));
+        s0 = _mm512_fmadd_pd(d0, d0, s0);
+        s1 = _mm512_fmadd_pd(d1, d1, s1);
     }
     for (; i + 8 <= D; i += 8) {
-        __m256 d0 = _mm256_sub_ps(_mm256_loadu_ps(a + i), _mm256_loadu_ps(b + i));
-        s0 = _mm256_fmadd_ps(d0, d0, s0);
+        __m512d d0 = _mm512_sub_pd(_mm512_loadu_pd(q + i), _mm512_cvtps_pd(_mm256_loadu_ps(x + i)));
+        s0 = _mm512_fmadd_pd(d0, d0, s0);
     }
-    float s = hsum256(_mm256_add_ps(s0, s1));
+    double s = _mm512_reduce_add_pd(_mm512_add_pd(s0, s1));
     for (; i < D; ++i) {
-        float d = a[i] - b[i];
+        const double d = q[i] - static_cast<double>(x[i]);
         s += d * d;
     }
-    return s;
+    return static_cast<float>(s);
 }
 
-__attribute__((target("avx2,fma"))) float ip_avx2(const float* a, const float* b, int D) {
-    __m256 s0 = _mm256_setzero_ps(), s1 = _mm256_setzero_ps();
+__attribute__((target("avx512f"))) float ip_avx512(const double* q, const float* x, int D) {
+    __m512d s0 = _mm512_setzero_pd(), s1 = _mm512_setzero_pd();
     int i = 0;
     for (; i + 16 <= D; i += 16) {
-        s0 = _mm256_fmadd_ps(_mm256_loadu_ps(a + i), _mm256_loadu_ps(b + i), s0);
-        s1 = _mm256_fmadd_ps(_mm256_loadu_ps(a + i + 8), _mm256_loadu_ps(b + i + 8), s1);
+        s0 = _mm512_fmadd_pd(_mm512_loadu_pd(q + i), _mm512_cvtps_pd(_mm256_loadu_ps(x + i)), s0);
+        s1 = _mm512_fmadd_pd(_mm512_loadu_pd(q + i + 8), _mm512_cvtps_pd(_mm256_loadu_ps(x + i + 8)), s1);
     }
-    for (; i + 8 <= D; i += 8) s0 = _mm256_fmadd_ps(_mm256_loadu_ps(a + i), _mm256_loadu_ps(b + i), s0);
-    float s = hsum256(_mm256_add_ps(s0, s1));
-    for (; i < D; ++i) s += a[i] * b[i];
-    return -s;
+    for (; i + 8 <= D; i += 8) s0 = _mm512_fmadd_pd(_mm512_loadu_pd(q + i), _mm512_cvtps_pd(_mm256_loadu_ps(x + i)), s0);
+    double s = _mm512_reduce_add_pd(_mm512_add_pd(s0, s1));
+    for (; i < D; ++i) s += q[i] * static_cast<double>(x[i]);
+    return static_cast<float>(-s);
 }
 
-__attribute__((target("avx512f"))) float l2_avx512(const float* a, const float* b, int D) {
-    __m512 s0 = _mm512_setzero_ps(), s1 = _mm512_setzero_ps();
-    int i = 0;
-    for (; i + 32 <= D; i += 32) {
-        __m512 d0 = _mm512_sub_ps(_mm512_loadu_ps(a + i), _mm512_loadu_ps(b + i));
-        __m512 d1 = _mm512_sub_ps(_mm512_loadu_ps(a + i + 16), _mm512_loadu_ps(b + i + 16));
-        s0 = _mm512_fmadd_ps(d0, d0, s0);
-        s1 = _mm512_fmadd_ps(d1, d1, s1);
-    }
-    for (; i + 16 <= D; i += 16) {
-        __m512 d0 = _mm512_sub_ps(_mm512_loadu_ps(a + i), _mm512_loadu_ps(b + i));
-        s0 = _mm512_fmadd_ps(d0, d0, s0);
-    }
-    float s = _mm512_reduce_add_ps(_mm512_add_ps(s0, s1));
-    for (; i < D; ++i) {
-        float d = a[i] - b[i];
-        s += d * d;
-    }
-    return s;
-}
-
-__attribute__((target("avx512f"))) float ip_avx512(const float* a, const float* b, int D) {
-    __m512 s0 = _mm512_setzero_ps(), s1 = _mm512_setzero_ps();
-    int i = 0;
-    for (; i + 32 <= D; i += 32) {
-        s0 = _mm512_fmadd_ps(_mm512_loadu_ps(a + i), _mm512_loadu_ps(b + i), s0);
-        s1 = _mm512_fmadd_ps(_mm512_loadu_ps(a + i + 16), _mm512_loadu_ps(b + i + 16), s1);
-    }
-    for (; i + 16 <= D; i += 16) s0 = _mm512_fmadd_ps(_mm512_loadu_ps(a + i), _mm512_loadu_ps(b + i), s0);
-    float s = _mm512_reduce_add_ps(_mm512_add_ps(s0, s1));
-    for (; i < D; ++i) s += a[i] * b[i];
-    return -s;
+// The query widened to fp64, one buffer per thread.
+const double* widen_query(const float* q, int D) {
+    thread_local std::vector<double> buf;
+    buf.assign(q, q + D);
+    return buf.data();
 }
 
 inline void prefetch_row(const float* p, int D) {
@@ -211,7 +215,7 @@ inline int offer(std::vector<Cand>& C, int ef, float d, int32_t v) {
 // Memory-level parallelism: the rows of all fresh neighbours are prefetched before any of
 // them is scored, and the adjacency row of the next unchecked candidate is prefetched
 // while the current one is processed (a guess: an insertion may still precede it).
-int run_steps(const StageContext& ctx, const HostGraph& g, const float* q, int ef, int max_steps,
+int run_steps(const StageContext& ctx, const HostGraph& g, const double* q, int ef, int max_steps,
               Visited& vis, std::vector<Cand>& C, int32_t& n_dist) {
     int steps = 0;
     size_t lb = 0;
@@ -282,11 +286,12 @@ void Visited::next_epoch() {
     }
 }
 
-void host_stages_one(const StageContext& ctx, const float* q, const int32_t* beam, int n_beam, int ef_cpu,
+void host_stages_one(const StageContext& ctx, const float* qf, const int32_t* beam, int n_beam, int ef_cpu,
                      int k, int refine_steps, Visited& vis, std::vector<Cand>& C, int64_t* out_ids,
                      float* out_d, StageCounters& cnt) {
     vis.next_epoch();
     C.clear();
+    const double* q = widen_query(qf, ctx.D);
     // stage 2: full distances of the handed-off candidates, re-rank, keep ef_cpu
     // all hand-off rows are requested before the first is scored
     constexpr int kAhead = 16;
@@ -314,10 +319,11 @@ void host_stages_one(const StageContext& ctx, const float* q, const int32_t* bea
     emit_topk(C, k, out_ids, out_d);
 }
 
-void host_search_one(const StageContext& ctx, const float* q, const int32_t* entries, int E, int ef, int k,
+void host_search_one(const StageContext& ctx, const float* qf, const int32_t* entries, int E, int ef, int k,
                      Visited& vis, std::vector<Cand>& C, int64_t* out_ids, float* out_d, StageCounters& cnt) {
     vis.next_epoch();
     C.clear();
+    const double* q = widen_query(qf, ctx.D);
     const int efe = std::max(ef, k);
     int32_t d3 = 0;
     for (int i = 0; i < E; ++i) {

@@ -13,32 +13,35 @@
 // reproduces Algorithm 1 with an exact visited set while holding only a bounded cache:
 // the cache never reports an unvisited node as visited (it stores full ids), it may only
 // forget nodes.  A forgotten node v that is met again is scored again; if v is still in
-// C its key is bit-identical (fixed reduction order) and the duplicate is dropped during
-// the merge, and if v had left C then C was full and its ef-th key has only decreased
-// since, so v is rejected again.  Either way C evolves exactly as in Algorithm 1; only
-// the count of distance evaluations can exceed |visited| (reported per query together
-// with the number of forget events).
+// C its key is bit-identical (the distance does not depend on lane placement) and the
+// duplicate is dropped during the merge, and if v had left C then C was full and its
+// ef-th key has only decreased since, so v is rejected again.  Either way C evolves
+// exactly as in Algorithm 1; only the count of distance evaluations can exceed |visited|
+// (reported per query together with the number of forget events).
 //
 // One loop step: find the first unchecked entry of C (one ballot per register), mark it
 // checked, take its adjacency row (one coalesced load of R ids, issued one step early for
-// the entry that was next in line when it still is), test-and-set the ids in
-// the cache, gather the reduced vectors of the new ids (16 bytes per lane, GS lanes per
-// vector, all loads in flight together), reduce each distance across its GS lanes with
-// DPP butterflies, drop candidates not better than C[ef-1] or already in C, rank the
-// survivors against C and against each other with ballots, and apply the merge as one
-// scatter to LDS and one gather back into the registers.
+// the entry that was next in line when it still is), test-and-set the ids in the cache,
+// gather the reduced vectors of the new ids (GS lanes per vector, 16 elements per lane,
+// all loads of a round in flight together), reduce each distance across its GS lanes
+// with DPP butterflies in float-float arithmetic (so the fp32 distance is the correctly
+// rounded exact one, which any other summation order also rounds to), drop candidates
+// not better than C[ef-1] or already in C, rank the survivors against C and against
+// each other with ballots, and apply the merge as one scatter to LDS and one gather back
+// into the registers.
 #include <hip/hip_runtime.h>
 
 #include <climits>
 
 #include "common.hpp"
+#include "ffloat.hpp"
 
 namespace pa {
 namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint64_t kInf = ~0ull;
-constexpr int kRounds = 4;  // gather rounds kept in flight per batch
+constexpr int kLaneElems = 16;  // vector elements each lane scores per gathered vector
 constexpr int kProbes = 16;
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
@@ -74,17 +77,23 @@ __device__ __forceinline__ float dpp(float v) {
     return __builtin_bit_cast(float,
                               __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
-// Sum over aligned groups of gs lanes.  Every lane of a group ends with the same value and
-// every group combines its lanes in the same order, so a vector's distance does not depend
-// on which group scored it.
-__device__ __forceinline__ float group_sum(float s, int gs) {
-    if (gs >= 2) s += dpp<0xB1>(s);   // quad_perm [1,0,3,2]: lane ^ 1
-    if (gs >= 4) s += dpp<0x4E>(s);   // quad_perm [2,3,0,1]: lane ^ 2
-    if (gs >= 8) s += dpp<0x141>(s);  // row_half_mirror: the other quad of the 8
-    if (gs >= 16) s += dpp<0x140>(s); // row_mirror: the other half of the 16
-    if (gs >= 32) s += __shfl_xor(s, 16);
-    if (gs >= 64) s += __shfl_xor(s, 32);
-    return s;
+template <int CTRL>
+__device__ __forceinline__ ff32 dpp(ff32 v) {
+    return ff32{dpp<CTRL>(v.hi), dpp<CTRL>(v.lo)};
+}
+__device__ __forceinline__ ff32 shfl_xor(ff32 v, int m) { return ff32{__shfl_xor(v.hi, m), __shfl_xor(v.lo, m)}; }
+// Float-float sum over aligned groups of gs lanes, returned rounded to fp32.  Every step
+// pairs two lanes with a symmetric addition, so every lane of a group ends with the same
+// bits, and a vector's distance does not depend on which group scored it.
+__device__ __forceinline__ float group_sum(ff32 s, int gs) {
+    if (gs >= 2) s = ff_add(s, dpp<0xB1>(s));   // quad_perm [1,0,3,2]: lane ^ 1
+    if (gs >= 4) s = ff_add(s, dpp<0x4E>(s));   // quad_perm [2,3,0,1]: lane ^ 2
+    if (gs >= 8) s = ff_add(s, dpp<0x141>(s));  // row_half_mirror: the other quad of the 8
+    if (gs >= 16) s = ff_add(s, dpp<0x140>(s)); // row_mirror: the other half of the 16
+    if (gs >= 32) s = ff_add(s, shfl_xor(s, 16));
+    if (gs >= 64) s = ff_add(s, shfl_xor(s, 32));
+    if (gs == 1) s = ff_norm(s);
+    return s.hi;
 }
 
 struct BeamArgs {
@@ -101,7 +110,7 @@ struct BeamArgs {
     int ef;             // list size, and the output row stride
     const int32_t* efq; // optional per-query list size (<= ef); entries used = min(E, efq[i])
     int hlog;
-    int gs_log;  // log2 of lanes per gathered vector
+    int gs_log;  // log2 of lanes per gathered vector (each lane holds kLaneElems elements)
     int cpr;     // 16-byte chunks per reduced row
     int wave_bytes;
     int32_t* out_ids;
@@ -156,6 +165,7 @@ constexpr int wave_lds_bytes(int hlog) {
 template <int DT, int MET, int CH>
 struct Wave {
     static constexpr int EPC = Chunk<DT>::kElems;
+    static constexpr int KC = kLaneElems / EPC;  // 16-byte chunks per lane per vector
 
     const BeamArgs& a;
     int lane, sub, grp, gs, vpl, hmask;
@@ -164,7 +174,7 @@ struct Wave {
     uint64_t* st_key;
     uint32_t* st_id;
     uint32_t* cache;
-    float qv[EPC];
+    float qv[KC][EPC];  // the query elements of this lane's chunks sub, sub + gs, ...
     int ef;
     int size = 0;
     int n_dist = 0;
@@ -186,7 +196,11 @@ struct Wave {
         for (int w = 0; w < CH; ++w) c[w] = kInf;
         const float* q = a.qr + qi * a.d_r;
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) qv[e] = (sub < a.cpr) ? q[sub * EPC + e] : 0.0f;
+        for (int j = 0; j < KC; ++j) {
+            const int ch = sub + j * gs;
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) qv[j][e] = (ch < a.cpr) ? q[ch * EPC + e] : 0.0f;
+        }
     }
 
     __device__ uint64_t key_at(int t) const {  // t uniform, t < CH * 64
@@ -233,17 +247,18 @@ struct Wave {
         wave_sync();
     }
 
-    __device__ float lane_partial(const uint4& raw) const {
-        float x[EPC];
-        Chunk<DT>::widen(raw, x);
-        float s = 0.0f;
+    // Float-float partial over this lane's chunks; chunks past the row are zero on both
+    // sides and add exactly nothing.
+    __device__ ff32 lane_partial(const uint4 (&raw)[KC]) const {
+        ff32 s{0.0f, 0.0f};
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) {
-            if (MET == PA_METRIC_L2) {
-                const float d = qv[e] - x[e];
-                s = __builtin_fmaf(d, d, s);
-            } else {
-                s = __builtin_fmaf(qv[e], x[e], s);
+        for (int j = 0; j < KC; ++j) {
+            float x[EPC];
+            Chunk<DT>::widen(raw[j], x);
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                if (MET == PA_METRIC_L2) ff_add_sqdiff(s, qv[j][e], x[e]);
+                else ff_add_prod(s, qv[j][e], x[e]);
             }
         }
         return s;
@@ -263,27 +278,22 @@ struct Wave {
         wave_sync();
         n_dist += n_new;
 
-        // gather and score, kRounds * vpl vectors per batch with all loads in flight
-        for (int b0 = 0; b0 < n_new; b0 += kRounds * vpl) {
-            uint4 raw[kRounds];
+        // gather and score vpl vectors per round: gs lanes per vector, KC 16-byte loads per
+        // lane (lane sub takes chunks sub, sub + gs, ...: every load instruction reads
+        // gs * 16 contiguous bytes of each of vpl rows), all loads of a round in flight
+        for (int b0 = 0; b0 < n_new; b0 += vpl) {
+            const int ci = b0 + grp;
+            const bool live = ci < n_new;
+            const unsigned char* row = a.xr + static_cast<int64_t>(live ? st_id[ci] : 0u) * a.row_bytes;
+            uint4 raw[KC];
 #pragma unroll
-            for (int rr = 0; rr < kRounds; ++rr) {
-                const int ci = b0 + rr * vpl + grp;
-                raw[rr] = make_uint4(0, 0, 0, 0);
-                if (ci < n_new && sub < a.cpr) {
-                    const uint32_t id = st_id[ci];
-                    raw[rr] = *reinterpret_cast<const uint4*>(a.xr + static_cast<int64_t>(id) * a.row_bytes +
-                                                              static_cast<int64_t>(sub) * 16);
-                }
+            for (int j = 0; j < KC; ++j) {
+                const int ch = sub + j * gs;
+                raw[j] = make_uint4(0, 0, 0, 0);
+                if (live && ch < a.cpr) raw[j] = *reinterpret_cast<const uint4*>(row + static_cast<int64_t>(ch) * 16);
             }
-#pragma unroll
-            for (int rr = 0; rr < kRounds; ++rr) {
-                if (b0 + rr * vpl >= n_new) break;
-                float s = (sub < a.cpr) ? lane_partial(raw[rr]) : 0.0f;
-                s = group_sum(s, gs);
-                const int ci = b0 + rr * vpl + grp;
-                if (sub == 0 && ci < n_new) st_key[ci] = make_key((MET == PA_METRIC_L2) ? s : -s, st_id[ci]);
-            }
+            const float s = group_sum(lane_partial(raw), gs);
+            if (sub == 0 && live) st_key[ci] = make_key((MET == PA_METRIC_L2) ? s : -s, st_id[ci]);
         }
         wave_sync();
 
@@ -521,13 +531,16 @@ void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dty
     a.ef = ef;
     a.hlog = cache_log2 > 0 ? cache_log2 : beam_auto_cache_log2(ef, R);
     a.cpr = static_cast<int>(a.row_bytes / 16);
+    // lanes per vector: enough lanes of kLaneElems elements (16 / element-size chunks) each
+    const int kc = kLaneElems / (16 / static_cast<int>(dtype_size(xr_dtype)));
     int gs_log = 0;
-    while ((1 << gs_log) < a.cpr) ++gs_log;
+    while ((1 << gs_log) * kc < a.cpr) ++gs_log;
     a.gs_log = gs_log;
     a.out_ids = ids;
     a.out_d = dists;
     a.counters = counters;
     require((1 << a.hlog) >= 4 * ((ef + 63) / 64 * 64), "visited cache must hold at least 4*ef entries");
+    require(a.row_bytes % 16 == 0, "reduced row must be a multiple of 16 bytes");
     require(a.cpr >= 1 && a.cpr <= 64, "reduced row must be 16..1024 bytes");
     if (xr_dtype == PA_F32) {
         if (metric == PA_METRIC_L2) launch_ch<PA_F32, PA_METRIC_L2>(a, s);

@@ -4,13 +4,15 @@
 // routed elsewhere.  Here the queries are first grouped by their routed cluster (a
 // counting sort into a preallocated permutation - no allocation, as section 5 asks), and
 // then every block works on one (cluster, 16-query tile) pair: a 16 x n_b x d product on
-// MFMA against that cluster's bucket of pivots, the distance epilogue fused, and a top-E
-// per query taken from LDS.  The m x n distance matrix D of Algorithm 2 is never stored.
+// MFMA against that cluster's bucket of pivots, the distance epilogue fused, a running
+// pre-selection per query in LDS, and an exact re-score of the pre-selected pivots before
+// the top-E is emitted.  The m x n distance matrix D of Algorithm 2 is never stored.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "common.hpp"
+#include "ffloat.hpp"
 
 namespace pa {
 namespace {
@@ -19,7 +21,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTQ = 16;          // queries per tile (MFMA rows)
 constexpr int kMaxClusters = 64;
-constexpr int kMaxNbPow2 = 512;  // LDS holds 16 x 512 keys
+constexpr int kRerankSlack = 16; // FP32 form pre-selects E + 16 pivots for the exact re-score
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
     uint32_t u = __float_as_uint(f);
@@ -73,127 +75,19 @@ __global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void score_kernel(const float* __restrict__ Qr, int d,
-                                                    const float* __restrict__ EV,
-                                                    const float* __restrict__ EVnorm,
-                                                    const int32_t* __restrict__ EVid, int r, int n_b,
-                                                    int nbp, int E, int metric,
-                                                    const int32_t* __restrict__ scratch,
-                                                    int32_t* __restrict__ out_ids, float* __restrict__ out_d) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    float* Aq = reinterpret_cast<float*>(smem);                       // [kTQ][d]
-    float* qn = Aq + kTQ * d;                                         // [kTQ]
-    uint64_t* keys = reinterpret_cast<uint64_t*>(qn + kTQ + 2);       // [kTQ][nbp] (8-byte aligned)
-    __shared__ int qidx[kTQ];
-    __shared__ int s_c, s_cnt;
-
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int w = t >> 6;
-    const int32_t* counts = scratch;
-    const int32_t* offsets = scratch + r;
-    const int32_t* tprefix = scratch + 2 * r + 1;
-    const int32_t* perm = scratch + 3 * r + 2;
-    const int b = blockIdx.x;
-    if (t == 0) {
-        int c = -1, cntq = 0;
-        if (b < tprefix[r]) {
-            c = 0;
-            while (c + 1 < r && tprefix[c + 1] <= b) ++c;
-            const int tile = b - tprefix[c];
-            const int base = offsets[c] + tile * kTQ;
-            cntq = min(kTQ, counts[c] - tile * kTQ);
-            for (int i = 0; i < kTQ; ++i) qidx[i] = (i < cntq) ? perm[base + i] : -1;
-        }
-        s_c = c;
-        s_cnt = cntq;
-    }
-    __syncthreads();
-    const int c = s_c;
-    if (c < 0) return;
-    const int cntq = s_cnt;
-    for (int idx = t; idx < kTQ * d; idx += 256) {
-        const int i = idx / d, j = idx - (idx / d) * d;
-        Aq[idx] = (i < cntq) ? Qr[static_cast<int64_t>(qidx[i]) * d + j] : 0.0f;
-    }
-    __syncthreads();
-    if (t < kTQ) {
-        float s = 0.0f;
-        for (int j = 0; j < d; ++j) s = __builtin_fmaf(Aq[t * d + j], Aq[t * d + j], s);
-        qn[t] = s;
-    }
-    __syncthreads();
-
-    const float* ev = EV + static_cast<int64_t>(c) * n_b * d;
-    const float* evn = EVnorm + static_cast<int64_t>(c) * n_b;
-    const int32_t* evid = EVid + static_cast<int64_t>(c) * n_b;
-    const int nblk = (nbp + 15) / 16;
-    for (int pb = w; pb < nblk; pb += 4) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const int p = pb * 16 + (lane & 15);
-        const bool pv = p < n_b;
-        for (int k = 0; k < d; k += 4) {
-            const float a = Aq[(lane & 15) * d + k + (lane >> 4)];
-            const float bb = pv ? ev[static_cast<int64_t>(p) * d + k + (lane >> 4)] : 0.0f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = 4 * (lane >> 4) + i;
-            uint64_t key = ~0ull;
-            if (pv && p < nbp) {
-                const float dot = acc[i];
-                const float dist = (metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[row] + evn[p]) : -dot;
-                key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(evid[p]);
-            }
-            if (p < nbp) keys[row * nbp + p] = key;
-        }
-    }
-    __syncthreads();
-
-    // top-E per query: bitonic sort of the row's keys by one wave, then the first E
-    for (int row = w; row < cntq; row += 4) {
-        uint64_t* s = keys + row * nbp;
-        for (int k = 2; k <= nbp; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = lane; i < nbp; i += 64) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const uint64_t x = s[i], y = s[l];
-                        const bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            s[i] = y;
-                            s[l] = x;
-                        }
-                    }
-                }
-                wave_sync();
-            }
-        }
-        const int64_t q = qidx[row];
-        for (int e = lane; e < E; e += 64) {
-            int32_t id = -1;
-            float dist = __builtin_huge_valf();
-            if (e < n_b) {
-                const uint64_t key = s[e];
-                id = static_cast<int32_t>(key & 0xFFFFFFFFu);
-                dist = unord_f32(static_cast<uint32_t>(key >> 32));
-            }
-            out_ids[q * E + e] = id;
-            out_d[q * E + e] = dist;
-        }
-    }
-}
-
-// ---------------------------------------------------------------- chunked variant
-// Any bucket size, and the FP8 form.  The bucket is scanned in chunks of CH pivots; each
-// query row keeps its best K keys in the first K slots of an LDS work row of P (a power of
-// two >= K + CH) keys, the chunk's keys land in the next CH slots, and the owning wave
-// re-sorts the row (bitonic).  FP32 form: K = E, keys carry node ids.  FP8 form: queries
-// are encoded per row like the pivots (scale = max|q| / 448, e4m3 round to nearest even),
-// the chunk is scored with v_mfma_f32_16x16x32_fp8_fp8 into an approximate distance, the
-// best K (a multiple of E) keys carry the pivot's index in its bucket, and those K are
-// re-scored exactly in fp32 (direct form) before the top E is emitted.
+// ---------------------------------------------------------------- pivot scoring
+// Any bucket size.  The bucket is scanned in chunks of CH pivots; each query row keeps its
+// best K keys in the first K slots of an LDS work row of P (a power of two >= K + CH)
+// keys, the chunk's keys land in the next CH slots, and the owning wave re-sorts the row
+// (bitonic).  The chunk is scored on MFMA into an approximate distance in the expanded
+// form |q|^2 + |p|^2 - 2 q.p (FP32 form: v_mfma_f32_16x16x4f32; FP8 form: queries encoded
+// per row like the pivots, scale = max|q| / 448, e4m3 round to nearest even, then
+// v_mfma_f32_16x16x32_fp8_fp8).  Pre-selection keys carry the pivot's index in its bucket.
+// The K pre-selected pivots are then re-scored in the direct form with float-float
+// arithmetic, so the emitted distances are the correctly rounded fp32 ones, and the top E
+// by (distance, node id) is emitted.  FP32 form: K = E + 16, so an exact top-E member is
+// lost only if more than 16 pivots fall within the expanded form's rounding error of it;
+// FP8 form: K is a multiple of E that absorbs the e4m3 error.
 typedef long fp8x8 __attribute__((ext_vector_type(1)));
 
 __device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
@@ -251,7 +145,7 @@ __device__ void bitonic_row(uint64_t* s, int n, int lane) {
 }
 
 template <bool FP8>
-__global__ __launch_bounds__(256) void score_chunked_kernel(FesArgs a) {
+__global__ __launch_bounds__(256) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int d = a.d;
     float* Aq = reinterpret_cast<float*>(smem);          // [kTQ][d]
@@ -338,8 +232,7 @@ __global__ __launch_bounds__(256) void score_chunked_kernel(FesArgs a) {
                     const float dot = FP8 ? acc[i] * (qs[row] * a.EVscale[cb + p]) : acc[i];
                     const float dist = (a.metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[row] + a.EVnorm[cb + p])
                                                                   : -dot;
-                    const uint32_t low = FP8 ? static_cast<uint32_t>(p) : static_cast<uint32_t>(a.EVid[cb + p]);
-                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | low;
+                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(p);
                 }
                 work[row * P + K + pb * 16 + (lane & 15)] = key;
             }
@@ -355,31 +248,27 @@ __global__ __launch_bounds__(256) void score_chunked_kernel(FesArgs a) {
 
     for (int row = w; row < cntq; row += 4) {
         uint64_t* s = work + row * P;
-        if (FP8) {
-            // exact fp32 re-rank of the K pre-selected pivots (direct form), keys by node id
-            for (int j = lane; j < P; j += 64) {
-                uint64_t key = ~0ull;
-                if (j < K && s[j] != ~0ull) {
-                    const int p = static_cast<int>(s[j] & 0xFFFFFFFFu);
-                    const float* pv = a.EV + (cb + p) * d;
-                    const float* qv = Aq + row * d;
-                    float acc = 0.0f;
-                    for (int k = 0; k < d; ++k) {
-                        if (a.metric == PA_METRIC_L2) {
-                            const float df = qv[k] - pv[k];
-                            acc = __builtin_fmaf(df, df, acc);
-                        } else {
-                            acc = __builtin_fmaf(qv[k], pv[k], acc);
-                        }
-                    }
-                    const float dist = (a.metric == PA_METRIC_L2) ? acc : -acc;
-                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
+        // re-score the K pre-selected pivots in the direct form, keys by node id
+        for (int j = lane; j < P; j += 64) {
+            uint64_t key = ~0ull;
+            if (j < K && s[j] != ~0ull) {
+                const int p = static_cast<int>(s[j] & 0xFFFFFFFFu);
+                const float* pv = a.EV + (cb + p) * d;
+                const float* qv = Aq + row * d;
+                ff32 acc{0.0f, 0.0f};
+                if (a.metric == PA_METRIC_L2) {
+                    for (int k = 0; k < d; ++k) ff_add_sqdiff(acc, qv[k], pv[k]);
+                } else {
+                    for (int k = 0; k < d; ++k) ff_add_prod(acc, qv[k], pv[k]);
                 }
-                s[j] = key;
+                const float v = ff_norm(acc).hi;
+                const float dist = (a.metric == PA_METRIC_L2) ? v : -v;
+                key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
             }
-            wave_sync();
-            bitonic_row(s, P, lane);
+            s[j] = key;
         }
+        wave_sync();
+        bitonic_row(s, P, lane);
         const int64_t q = qidx[row];
         for (int e = lane; e < a.E; e += 64) {
             int32_t id = -1;
@@ -406,7 +295,7 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     require(r >= 1 && r <= kMaxClusters, "FES supports 1..64 clusters");
     const bool fp8 = EV8 != nullptr;
     if (fp8) require(d % 32 == 0, "FP8 entry selection needs d % 32 == 0", PA_EUNSUPPORTED);
-    if (!fp8) K = E;
+    if (!fp8) K = E + kRerankSlack;
     K = std::max(K, E);
     int dev = 0, max_lds = 64 * 1024;
     PA_HIP(hipGetDevice(&dev));
@@ -427,31 +316,16 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     PA_HIP(hipGetLastError());
     FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, CH, P, metric, scratch_i32, ids, dists};
     const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
-    if (fp8) hipLaunchKernelGGL(score_chunked_kernel<true>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
-    else hipLaunchKernelGGL(score_chunked_kernel<false>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
+    if (fp8) hipLaunchKernelGGL(score_kernel<true>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
+    else hipLaunchKernelGGL(score_kernel<false>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
     PA_HIP(hipGetLastError());
 }
 
 void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
                            const float* EVnorm, const int32_t* EVid, int r, int n_b, int E, int metric,
                            int32_t* ids, float* dists, int32_t* scratch_i32, hipStream_t s) {
-    if (m == 0) return;
-    require(r >= 1 && r <= kMaxClusters, "FES supports 1..64 clusters");
-    int nbp = 1;
-    while (nbp < n_b) nbp <<= 1;
-    if (nbp < 16) nbp = 16;
-    if (nbp > kMaxNbPow2 || sizeof(float) * (kTQ * d + kTQ + 2) + sizeof(uint64_t) * kTQ * nbp > 64 * 1024) {
-        launch_select_entries_chunked(Qr, cluster, m, d, EV, nullptr, nullptr, EVnorm, EVid, r, n_b, E, E, metric,
-                                      ids, dists, scratch_i32, s);
-        return;
-    }
-    hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
-    PA_HIP(hipGetLastError());
-    const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
-    const size_t lds = sizeof(float) * (kTQ * d + kTQ + 2) + sizeof(uint64_t) * kTQ * nbp;
-    hipLaunchKernelGGL(score_kernel, dim3(max_tiles), dim3(256), lds, s, Qr, d, EV, EVnorm, EVid, r, n_b,
-                       nbp, E, metric, scratch_i32, ids, dists);
-    PA_HIP(hipGetLastError());
+    launch_select_entries_chunked(Qr, cluster, m, d, EV, nullptr, nullptr, EVnorm, EVid, r, n_b, E, E, metric, ids,
+                                  dists, scratch_i32, s);
 }
 
 }  // namespace pa

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "ffloat.hpp"
 
 namespace pa {
 namespace {
@@ -105,12 +106,9 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Qr
     float best = __builtin_huge_valf();
     if (lane < r) {
         const float* cv = C + static_cast<int64_t>(lane) * d_r;
-        float s = 0.0f;
-        for (int j = 0; j < d_r; ++j) {
-            const float d = qv[j] - cv[j];
-            s = __builtin_fmaf(d, d, s);
-        }
-        best = s;
+        ff32 s{0.0f, 0.0f};
+        for (int j = 0; j < d_r; ++j) ff_add_sqdiff(s, qv[j], cv[j]);
+        best = ff_norm(s).hi;  // the correctly rounded fp32 distance
     }
     // (distance, index) minimum across the wave, lowest index on ties
     uint64_t key = (static_cast<uint64_t>(__float_as_uint(best)) << 32) | static_cast<uint32_t>(lane);

@@ -11,6 +11,7 @@ import pytest
 import oracle
 import paper_2503_21206_amd as pa
 from synth.data import gmm_points, make_rng
+from tests.parity import TIE, DistTally
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -162,21 +163,25 @@ def test_cpu_stages_match_oracle(tiny):
     for steps, ef_cpu, k in ((2, 32, 10), (0, 16, 10), (-1, 24, 30)):
         ids, d, cnt = pa.cpu_stages(X, tiny["sub_adj"], tiny["adj"], Q, beams, ef_cpu, k, steps, threads=4)
         bad = 0
+        tally = DistTally()
         for i in range(Q.shape[0]):
+            m2 = np.inf
             if steps >= 0:
                 r = oracle.refine(Q[i], X, tiny["sr"], tiny["sn"], beams[i], ef_cpu, steps=steps)
-                c_ids, c_d, vis, n2 = r["ids"], r["dists"], r["visited"], r["n_dist"]
+                c_ids, c_d, vis, n2, m2 = r["ids"], r["dists"], r["visited"], r["n_dist"], r["margin"]
             else:
                 b = beams[i][beams[i] >= 0]
-                c_d = oracle.delta_many(Q[i], X[b])
+                c_d = oracle.as_f32(oracle.delta_many(Q[i], X[b]))
                 c_ids, vis, n2 = b, set(b.tolist()), b.size
             oi, od, f = oracle.final_traversal(Q[i], X, tiny["rp"], tiny["nb"], c_ids, c_d, vis, ef_cpu, k)
-            same = (ids[i] == oi).all()
-            if not same:
+            if not (ids[i] == oi).all():
+                assert min(m2, f["margin"]) <= TIE, (i, m2, f["margin"])
                 bad += 1
                 continue
-            np.testing.assert_allclose(d[i], od, rtol=2e-6)
-            assert cnt[i, 0] == n2 and cnt[i, 1] == f["n_dist"] and cnt[i, 2] == f["n_exp"]
+            tally.check(d[i], od, i)
+            if min(m2, f["margin"]) > TIE:
+                assert cnt[i, 0] == n2 and cnt[i, 1] == f["n_dist"] and cnt[i, 2] == f["n_exp"]
+        tally.done()
         assert bad <= max(1, Q.shape[0] // 1000), bad
 
 
@@ -184,13 +189,19 @@ def test_cpu_search_is_plain_greedy_search(tiny):
     X, Q = tiny["X"], tiny["Q"]
     entries = np.tile(np.array([0, 4000, 9999], dtype=np.int32), (Q.shape[0], 1))
     ids, d, cnt = pa.cpu_search(X, tiny["adj"], Q, entries, 40, 10, threads=3)
+    tally = DistTally()
+    bad = 0
     for i in range(Q.shape[0]):
         r = oracle.greedy_search(Q[i], X, tiny["rp"], tiny["nb"], 40, entries[i])
         if (ids[i] == r["ids"][:10]).all():
-            assert cnt[i, 1] == r["n_dist"] and cnt[i, 2] == r["n_exp"]
-            np.testing.assert_allclose(d[i], r["dists"][:10], rtol=2e-6)
+            tally.check(d[i], r["dists"][:10], i)
+            if r["margin"] > TIE:
+                assert cnt[i, 1] == r["n_dist"] and cnt[i, 2] == r["n_exp"]
         else:
-            assert r["margin"] < 2e-5
+            assert r["margin"] <= TIE
+            bad += 1
+    tally.done()
+    assert bad <= max(1, Q.shape[0] // 1000), bad
 
 
 def test_cpu_stages_hand_example(golden_dir):
@@ -202,7 +213,7 @@ def test_cpu_stages_hand_example(golden_dir):
     ids, d, cnt = pa.cpu_stages(X, sub, full, np.array([g["query"]], dtype=np.float32),
                                 np.array([g["beam"]], dtype=np.int32), g["ef_cpu"], g["k"], g["steps"], threads=1)
     assert ids[0].tolist() == g["final_ids"]
-    np.testing.assert_allclose(d[0], g["final_dists"], rtol=1e-6)
+    np.testing.assert_allclose(d[0], g["final_dists"], rtol=2.0 ** -23)  # fp32 rounding of the worked values
     assert cnt[0].tolist() == [g["refine_n_dist"], g["final_n_dist"], g["final_n_exp"], 0]
 
 

@@ -1,12 +1,14 @@
 """GPU parity: every stage-isolated entry point against the oracle on the same
 seeded inputs (the 10K x 96 workload: several tiles, a ragged tail), plus edge
-cases.  Tolerances (from the fp32 arithmetic of the kernels):
-* distances: |d_gpu - d_64| <= 1e-5 * d_64 for the direct L2 form, 1e-5 *
-  (|q|^2 + |x|^2) for the expanded GEMM form, 1e-5 * |q||x| for inner product;
-* ids: the ordered list equals the oracle's on >= 99.9% of queries, and a
-  query may differ only if the oracle's near-tie margin is below 2e-5;
+cases.  The bar (see tests/parity.py for the reasoning):
+* distances: the correctly rounded fp32 value on both sides, so within 1 ulp of
+  the oracle's everywhere and identical on all but a 1e-4 fraction;
+* ids: the ordered list equals the oracle's; a query may differ only where the
+  oracle's near-tie margin is at most two ulps, and on at most 0.1% of queries;
 * counters equal wherever the ids are equal, no near tie occurred and the
   visited cache never reset.
+Where the library's own projection feeds a stage (routing), its fp32 GEMM
+error bound is the tolerance instead.
 """
 
 import numpy as np
@@ -14,12 +16,11 @@ import pytest
 
 import oracle
 import paper_2503_21206_amd as pa
+from tests.parity import TIE, DistTally
 from tests.workload import build_tiny, device_tables, oracle_entries, to_bf16, to_f16
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-TIE = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -113,24 +114,19 @@ def test_route(dev, tiny):
 
 def _fes_check(dev, w, E, Qr, metric="l2"):
     EV, EVn, EVid = device_tables(w)
-    oi, od, ocl, _ = oracle_entries(w, E, Qr)
-    _, od1, _, _ = oracle_entries(w, min(E + 1, EV.shape[1]), Qr)
+    oi, od, ocl, margin = oracle_entries(w, E, Qr)
     ids, d = pa.select_entries(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EVn, dev),
                                _t(EVid, dev), E, metric)
     ids, d = ids.cpu().numpy(), d.cpu().numpy()
-    pn = float(EVn.max())
+    tally = DistTally()
     bad = 0
     for i in range(Qr.shape[0]):
-        scale = float((Qr[i].astype(np.float64) ** 2).sum()) + pn
-        tol = 1e-5 * scale
-        fin = oi[i] >= 0
         if not (ids[i] == oi[i]).all():
-            gaps = np.diff(od1[i][np.isfinite(od1[i])])
-            assert gaps.size and gaps.min() < 2 * tol, (i, ids[i], oi[i])
+            assert margin[i] <= TIE, (i, ids[i], oi[i], margin[i])
             bad += 1
             continue
-        assert (np.abs(d[i][fin] - od[i][fin]) <= tol).all()
-        assert (d[i][~fin] == np.inf).all()
+        tally.check(d[i], od[i], i)
+    tally.done()
     return bad
 
 
@@ -154,6 +150,7 @@ def _traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cac
     assert (cnt[:, 3] == 0).all()
     Xr64 = Xr_host.astype(np.float64)
     bad = 0
+    tally = DistTally()
     n = Xr_host.shape[0]
     for j, i in enumerate(qidx):
         ent_i = np.where((entries[i] >= 0) & (entries[i] < n), entries[i], -1)  # the kernel skips the others
@@ -162,22 +159,19 @@ def _traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cac
         ref = np.full(ef, -1)
         ref[:k] = r["ids"]
         if not (ids[j] == ref).all():
-            assert r["margin"] < TIE, (i, ids[j][:8], ref[:8], r["margin"])
+            assert r["margin"] <= TIE, (i, ids[j][:8], ref[:8], r["margin"])
             bad += 1
             continue
         assert (ids[j][k:] == -1).all() and (d[j][k:] == np.inf).all()
-        if metric == "l2":
-            assert (np.abs(d[j][:k] - r["dists"]) <= 1e-5 * r["dists"] + 1e-30).all()
-        else:
-            qn = np.linalg.norm(Qr[j].astype(np.float64))
-            xn = np.linalg.norm(Xr64[r["ids"]], axis=1)
-            assert (np.abs(d[j][:k] - r["dists"]) <= 1e-5 * qn * xn).all()
-        if r["margin"] >= TIE:
+        tally.check(d[j][:k], r["dists"], i)
+        if r["margin"] > TIE:
             assert cnt[j, 0] == r["n_exp"]
             if cnt[j, 2] == 0:
                 assert cnt[j, 1] == r["n_dist"]
             else:
                 assert cnt[j, 1] >= r["n_dist"]
+    off = tally.done()
+    say(f"  {len(qidx)} queries: {bad} id divergences, {off} of {tally.n} distances 1 ulp off")
     if expect_reset:
         assert (cnt[:, 2] > 0).any()
     assert bad <= max(1, len(qidx) // 1000), bad
@@ -291,9 +285,11 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     assert rec >= orec - 0.02
     same = np.mean([(ids[i] == oi[i]).all() for i in range(200)])
     assert same >= 0.97
-    # final distances are exact full fp32 distances
-    full = np.stack([oracle.delta_many(Q[i], tiny["X"][ids[i]]) for i in range(50)])
-    np.testing.assert_allclose(d[:50], full, rtol=2e-6)
+    # final distances are the correctly rounded full-vector distances
+    tally = DistTally()
+    for i in range(200):
+        tally.check(d[i], oracle.as_f32(oracle.delta_many(Q[i], tiny["X"][ids[i]])), i)
+    tally.done()
     # graceful degradation: no GPU stage = plain greedy search from the FES entries
     ids0, _, cnt0, _ = idx.search(Q[:100], 10, 64, 64, stage_mask=2, with_counters=True)
     assert (cnt0[:, 0] == 0).all()
@@ -321,18 +317,19 @@ def test_select_entries_chunked_large_bucket(dev, tiny):
     P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny)
     Qr = tiny["Qr32"][:300]
     oi, od, ocl, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 32)
-    _, od1, _, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 33)
     ids, d = pa.select_entries(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EVn, dev), _t(EVid, dev),
                                32)
     ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    _, _, _, margin = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 32)
+    tally = DistTally()
     bad = 0
     for i in range(Qr.shape[0]):
-        tol = 1e-5 * (float((Qr[i].astype(np.float64) ** 2).sum()) + float(EVn.max()))
         if not (ids[i] == oi[i]).all():
-            assert np.diff(od1[i]).min() < 2 * tol
+            assert margin[i] <= TIE, (i, margin[i])
             bad += 1
             continue
-        assert (np.abs(d[i] - od[i]) <= tol).all()
+        tally.check(d[i], od[i], i)
+    tally.done()
     assert bad <= 1
 
 
@@ -351,11 +348,12 @@ def test_select_entries_fp8_preselect_then_fp32_rerank(dev, tiny):
     exact = np.mean([(ids[i] == oi[i]).all() for i in range(Qr.shape[0])])
     say(f"fp8 pre-selection: overlap@16 {overlap:.4f}, identical lists {exact:.4f}")
     assert overlap >= 0.99
-    # every returned distance is the exact fp32 direct-form distance of its pivot
+    # every returned distance is the correctly rounded fp32 distance of its pivot
     Xr64 = tiny["Xr32"].astype(np.float64)
+    tally = DistTally()
     for i in range(Qr.shape[0]):
-        ref = ((Xr64[ids[i]] - Qr[i].astype(np.float64)) ** 2).sum(1)
-        assert (np.abs(d[i] - ref) <= 1e-5 * ref).all()
+        tally.check(d[i], oracle.as_f32(oracle.delta_many(Qr[i], Xr64[ids[i]])), i)
+    tally.done()
 
 
 def test_index_with_fp8_pivots(dev, tiny):

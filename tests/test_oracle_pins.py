@@ -128,7 +128,7 @@ def test_traverse_hand_examples(golden_dir):
         r = oracle.greedy_search(np.array(c["query"]), np.array(c["points"], dtype=np.float64),
                                  rowptr, nbrs, c["ef"], c["entries"])
         assert r["ids"].tolist() == c["ids"], c["name"]
-        np.testing.assert_allclose(r["dists"], c["dists"], atol=1e-12, err_msg=c["name"])
+        np.testing.assert_allclose(r["dists"], c["dists"], rtol=1e-7, atol=0, err_msg=c["name"])
         assert r["n_exp"] == c["n_exp"], c["name"]
         assert r["n_dist"] == c["n_dist"], c["name"]
 
@@ -146,10 +146,13 @@ def test_large_ef_returns_exact_knn_of_reachable_set():
     Q = gmm_points(22, 15, 10, 3, stream_offset=1)
     gt, gd = oracle.exact_knn(X, Q, 10)
     for i, q in enumerate(Q):
-        r = oracle.greedy_search(q, X, rowptr, nbrs, X.shape[0], [0])
+        r = oracle.greedy_search(q, X, rowptr, nbrs, X.shape[0], [0], precision="f64")
         assert r["n_dist"] == X.shape[0]  # the repaired graph reaches every node
         assert r["ids"][:10].tolist() == gt[i].tolist()
         np.testing.assert_allclose(r["dists"][:10], gd[i], rtol=1e-12)
+        # in the paper's single precision the distances are the fp32-rounded exact ones
+        r32 = oracle.greedy_search(q, X, rowptr, nbrs, X.shape[0], [0])
+        assert (r32["dists"][:10] == gd[i].astype(np.float32).astype(np.float64)).all()
 
 
 def test_complete_graph_one_expansion_sees_everything():
@@ -334,11 +337,18 @@ def test_one_cluster_is_brute_force_over_pivots():
     pid = np.arange(1000, 1096)
     b, c = oracle.balanced_kmeans(P, 1, [0])
     ids, d, cl, _ = oracle.select_entries(Q, c, b, P, pid, 10)
-    full = cdist(Q.astype(np.float64), P.astype(np.float64), "sqeuclidean")
+    # single-precision keys: the exact distance rounded once to fp32, ties by node id
+    full = cdist(Q.astype(np.float64), P.astype(np.float64), "sqeuclidean").astype(np.float32)
     for i in range(Q.shape[0]):
-        ref = np.argsort(full[i], kind="stable")[:10]
+        ref = np.lexsort((pid, full[i]))[:10]
         assert ids[i].tolist() == (pid[ref]).tolist()
-        np.testing.assert_allclose(d[i], full[i][ref], rtol=1e-12)
+        assert (d[i] == full[i][ref]).all()
+    ids64, d64, _, _ = oracle.select_entries(Q, c, b, P, pid, 10, precision="f64")
+    full64 = cdist(Q.astype(np.float64), P.astype(np.float64), "sqeuclidean")
+    for i in range(Q.shape[0]):
+        ref = np.argsort(full64[i], kind="stable")[:10]
+        assert ids64[i].tolist() == (pid[ref]).tolist()
+        np.testing.assert_allclose(d64[i], full64[i][ref], rtol=1e-12)
 
 
 def test_fes_work_matches_complexity_table():
@@ -377,9 +387,10 @@ def test_refine_without_steps_is_a_rerank_by_full_distance():
     beam = [5, 99, 17, 250, -1]
     r = oracle.refine(q, X, rowptr, nbrs, beam, 3, steps=0)
     full = cdist(q[None].astype(np.float64), X[[5, 99, 17, 250]].astype(np.float64), "sqeuclidean")[0]
+    full = full.astype(np.float32)  # single-precision keys, rounded once
     order = np.argsort(full, kind="stable")[:3]
     assert r["ids"].tolist() == [[5, 99, 17, 250][i] for i in order]
-    np.testing.assert_allclose(r["dists"], full[order], rtol=1e-12)
+    assert (r["dists"] == full[order]).all()
 
 
 def test_graceful_degradation_is_plain_greedy_search_and_exact_at_large_ef():
