@@ -16,7 +16,12 @@ algorithmic bytes per query are 4*d_r (query) + 4*E (entries) + 4*R per
 expansion (adjacency row) + s*d_r per distance evaluation (gathered reduced
 row, s = bytes per element) + 8*ef (list out), from the kernel's own counters;
 the launch duration comes from HIP events recorded around every launch on the
-library's stream during the timed steps.  Peak = 8 TB/s HBM.
+library's stream during the timed steps.  Peak = 8 TB/s HBM.  ``traffic`` is the
+HBM traffic per launch that rocprofv3's FETCH_SIZE and WRITE_SIZE counters
+measured for the same kernel and configuration, each scaled by what the counter
+reads for a copy of known size; it is read from the committed counter summary
+and reported only while the kernel's sources still hash to the value recorded
+there (null otherwise).
 """
 
 from __future__ import annotations
@@ -33,6 +38,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "beam_kernel_gmm1m_traffic.txt")
+BEAM_SOURCES = ("k_beam.hip", "ffloat.hpp", "common.hpp")
+
+
+def beam_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in BEAM_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_21206_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, form, ef_gpu):
+    """Counter-measured HBM bytes per beam launch, if the summary matches this kernel and run."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if (kv.get("source_hash") != beam_source_hash() or kv.get("workload") != workload
+            or kv.get("form") != form or kv.get("ef_gpu") != str(ef_gpu)):
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def log(msg):
@@ -139,7 +169,7 @@ def timed(idx, spec, fx, ef, steps, warmup):
     return dt, agg, rec
 
 
-def roofline(spec, agg, steps, ef, E, xr_bytes):
+def roofline(spec, agg, steps, ef, E, xr_bytes, form):
     """Beam-kernel bytes and time per launch; ef is the stage-1 list size."""
     m = spec.queries * steps
     algo = (m * (4 * spec.d_r + 4 * E + 8 * ef) + agg["n_exp1"] * 4 * spec.degree
@@ -149,7 +179,7 @@ def roofline(spec, agg, steps, ef, E, xr_bytes):
     avg_ms = agg["beam_ms"] / launches
     achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(spec.name, form, ef),
             "kernel": "beam_kernel", "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(avg_ms, 4),
             "launches": int(launches)}
 
@@ -251,7 +281,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-budget", type=int, default=32 << 30)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="end with a 1 GiB device-to-device copy (counter calibration for profiles)")
+                    help="end with a 1 GiB device-to-device copy kernel (counter calibration for profiles)")
+    ap.add_argument("--ef", default="",
+                    help="ef_gpu,ef_cpu to time directly instead of sweeping for the target recall")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -271,8 +303,11 @@ def main():
     serving = None
     for form in args.forms.split(","):
         idx = build_index(spec, fx, form, shared)
-        log(f"sweep {form}")
-        ef, curve = sweep(idx, spec, fx, args.target, spec.ef)
+        if args.ef:
+            ef, curve = tuple(int(x) for x in args.ef.split(",")), []
+        else:
+            log(f"sweep {form}")
+            ef, curve = sweep(idx, spec, fx, args.target, spec.ef)
         if ef is None:
             ef = (spec.ef[-1], spec.ef[-1])
             log(f"  target recall not reached; timing at ef={ef}")
@@ -283,7 +318,7 @@ def main():
         forms[form] = {
             "value": round(qps, 1), "ef_gpu": ef[0], "ef_cpu": ef[1], "recall": round(rec, 5),
             "ms_per_step": round(dt * 1e3 / args.steps, 3),
-            "roofline": roofline(spec, agg, args.steps, ef[0], E, xr_bytes),
+            "roofline": roofline(spec, agg, args.steps, ef[0], E, xr_bytes, form),
             "gpu_stage": {"beam_ms_per_step": round(agg["beam_ms"] / args.steps, 3),
                           "fes_ms_per_step": round(agg["fes_ms"] / args.steps, 3),
                           "host_wait_ms_per_step": round(agg["host_wait_ms"] / args.steps, 3),
@@ -325,7 +360,8 @@ def main():
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
 
