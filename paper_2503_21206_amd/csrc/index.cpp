@@ -131,7 +131,15 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
 
     int64_t& hb = idx->hbm_used;
     const int64_t bud = idx->p.hbm_budget;
-    auto* q_dev = static_cast<float*>(idx->w_q.ensure(sizeof(float) * m * D, hb, bud));
+    if (o.q_dev) {
+        hipPointerAttribute_t pa{};
+        const bool ok = hipPointerGetAttributes(&pa, o.q_dev) == hipSuccess && pa.type == hipMemoryTypeDevice &&
+                        pa.device == idx->p.device;
+        (void)hipGetLastError();  // a failed query leaves no error behind
+        require(ok, "q_dev must be device memory on the index's device");
+    }
+    float* q_dev = o.q_dev ? nullptr : static_cast<float*>(idx->w_q.ensure(sizeof(float) * m * D, hb, bud));
+    const float* q_src = o.q_dev ? o.q_dev : q_dev;
     auto* qr_dev = static_cast<float*>(idx->w_qr.ensure(sizeof(float) * m * d_r, hb, bud));
     auto* cl_dev = static_cast<int32_t*>(idx->w_cl.ensure(sizeof(int32_t) * m, hb, bud));
     auto* eid_dev = static_cast<int32_t*>(idx->w_eid.ensure(sizeof(int32_t) * m * E, hb, bud));
@@ -140,7 +148,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     auto* bd_dev = static_cast<float*>(idx->w_bd.ensure(sizeof(float) * m * ef, hb, bud));
     auto* cnt_dev = static_cast<int32_t*>(idx->w_cnt.ensure(sizeof(int32_t) * m * 4, hb, bud));
     auto* scr_dev = static_cast<int32_t*>(idx->w_scr.ensure(sizeof(int32_t) * select_entries_scratch_ints(B, r), hb, bud));
-    auto* q_pin = static_cast<float*>(idx->p_q.ensure(sizeof(float) * m * D));
+    auto* q_pin = o.q_dev ? nullptr : static_cast<float*>(idx->p_q.ensure(sizeof(float) * m * D));
     auto* beam_pin = static_cast<int32_t*>(idx->p_beam.ensure(sizeof(int32_t) * m * ef));
     auto* cnt_pin = static_cast<int32_t*>(idx->p_cnt.ensure(sizeof(int32_t) * m * 4));
     auto* ent_pin = static_cast<int32_t*>(idx->p_ent.ensure(sizeof(int32_t) * m * E));
@@ -151,10 +159,12 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     for (int64_t b = 0; b < nbatch; ++b) {
         const int64_t b0 = b * B, nb = std::min(B, m - b0);
         hipEvent_t* ev = &idx->events[static_cast<size_t>(4 * b)];
-        std::memcpy(q_pin + b0 * D, Q + b0 * D, sizeof(float) * nb * D);
-        PA_HIP(hipMemcpyAsync(q_dev + b0 * D, q_pin + b0 * D, sizeof(float) * nb * D, hipMemcpyHostToDevice, s));
+        if (o.q_dev == nullptr) {
+            std::memcpy(q_pin + b0 * D, Q + b0 * D, sizeof(float) * nb * D);
+            PA_HIP(hipMemcpyAsync(q_dev + b0 * D, q_pin + b0 * D, sizeof(float) * nb * D, hipMemcpyHostToDevice, s));
+        }
         PA_HIP(hipEventRecord(ev[0], s));
-        launch_project(q_dev + b0 * D, nb, D, static_cast<const float*>(idx->V_dev.p), d_r, qr_dev + b0 * d_r, PA_F32,
+        launch_project(q_src + b0 * D, nb, D, static_cast<const float*>(idx->V_dev.p), d_r, qr_dev + b0 * d_r, PA_F32,
                        static_cast<const float*>(idx->cent_dev.p), r, cl_dev + b0, s);
         index_select_entries(idx, qr_dev + b0 * d_r, cl_dev + b0, nb, E, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev, s);
         PA_HIP(hipEventRecord(ev[1], s));

@@ -290,6 +290,17 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     for i in range(200):
         tally.check(d[i], oracle.as_f32(oracle.delta_many(Q[i], tiny["X"][ids[i]])), i)
     tally.done()
+    # queries already resident in HBM: identical results, no upload
+    Qd = _t(Q, dev)
+    ids_d, d_d, _, _ = idx.search(Q, 10, 64, 64, batch=300, Q_dev=Qd)
+    assert (ids_d == ids).all() and (d_d.view(np.uint32) == d.view(np.uint32)).all()
+    import ctypes
+    opts = pa.SearchOpts(64, 64, 0, 0, 0, 0, 0, 0, Q.ctypes.data)  # a host pointer is refused
+    out_i = np.empty((Q.shape[0], 10), np.int64)
+    out_d = np.empty((Q.shape[0], 10), np.float32)
+    st = pa.lib().pa_search(idx._h, Q.ctypes.data_as(ctypes.c_void_p), Q.shape[0], 10, ctypes.byref(opts),
+                            out_i.ctypes.data_as(ctypes.c_void_p), out_d.ctypes.data_as(ctypes.c_void_p), None, None)
+    assert st == -1
     # graceful degradation: no GPU stage = plain greedy search from the FES entries
     ids0, _, cnt0, _ = idx.search(Q[:100], 10, 64, 64, stage_mask=2, with_counters=True)
     assert (cnt0[:, 0] == 0).all()
