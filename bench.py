@@ -172,6 +172,35 @@ def timed(idx, spec, fx, ef, steps, warmup):
     return dt, agg, rec
 
 
+def cpu_only(idx, spec, fx, target, steps):
+    """The library with the GPU stage switched off: plain Algorithm 1 on the full graph on
+    the host cores from the FES entries (graceful degradation, section 4.1), the analogue
+    of the CPU graph search the paper compares against.  Smallest swept ef reaching the
+    target recall, then `steps` timed searches."""
+    import torch
+    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
+    curve, chosen = [], None
+    for ef in sorted(set(spec.ef) | {24, 40, 80, 160}):
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef, stage_mask=2, Q_dev=Qd)
+        rec = recall(ids, fx["gt"], spec.k)
+        curve.append({"ef": ef, "recall": round(rec, 5), "qps": round(fx["Q"].shape[0] / (st["wall_ms"] / 1e3), 1)})
+        log(f"  cpu-only ef={ef:4d} recall@{spec.k}={rec:.4f}")
+        if rec >= target:
+            chosen = ef
+            break
+    if chosen is None:
+        return {"curve": curve, "value": None}
+    t0 = time.perf_counter()
+    agg = 0
+    for _ in range(steps):
+        ids, _, cnt, st = idx.search(fx["Q"], spec.k, chosen, chosen, stage_mask=2, Q_dev=Qd, with_counters=True)
+        agg += int(cnt[:, 4].sum())
+    dt = time.perf_counter() - t0
+    return {"value": round(spec.queries * steps / dt, 1), "unit": "queries/s", "ef": chosen,
+            "recall": round(recall(ids, fx["gt"], spec.k), 5), "mean_n_dist": round(agg / (spec.queries * steps), 1),
+            "curve": curve}
+
+
 def roofline(spec, agg, steps, ef, E, xr_bytes, form):
     """Beam-kernel bytes and time per launch; ef is the stage-1 list size."""
     m = spec.queries * steps
@@ -279,6 +308,7 @@ def main():
     ap.add_argument("--target", type=float, default=0.95)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-only", action="store_true", help="skip the GPU-stage-off comparison leg")
     ap.add_argument("--forms", default="f32,f16")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -304,6 +334,7 @@ def main():
     shared = {}
     forms = {}
     serving = None
+    baseline_cpu_only = None
     for form in args.forms.split(","):
         idx = build_index(spec, fx, form, shared)
         if args.ef:
@@ -333,6 +364,9 @@ def main():
             "curve": curve,
         }
         log(f"{form}: ef={ef} recall={rec:.4f} qps={qps:,.0f} roofline={forms[form]['roofline']}")
+        if form == "f32" and not args.no_cpu_only:
+            log("cpu-only (GPU stage off)")
+            baseline_cpu_only = cpu_only(idx, spec, fx, args.target, max(1, min(args.steps, 3)))
         if form == "f16" and args.serve_rates:
             rates = [float(x) for x in args.serve_rates.split(",") if x]
             serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
@@ -353,6 +387,13 @@ def main():
         "roofline": f["roofline"],
         "forms": forms,
     }
+    if baseline_cpu_only is not None:
+        co = dict(baseline_cpu_only)
+        co["what"] = ("this library with the GPU stage off: Algorithm 1 on the full graph on the host cores from "
+                      "the FES entries, smallest ef reaching the target recall")
+        if co.get("value"):
+            co["speedup_of_value"] = round(f["value"] / co["value"], 2)
+        out["cpu_only"] = co
     if serving is not None:
         out["serving"] = {"workload": f"{spec.name} index, fp16 reduced vectors; Poisson arrivals, k in "
                                       f"{{10,50,100}}, ef in {{64,128,256,512}}, {args.serve_seconds}s per rate, "

@@ -48,6 +48,7 @@ typedef int32_t pa_status;
 #define PA_ENONFINITE (-6)   /* NaN or Inf in an input that must be finite        */
 #define PA_EUNSUPPORTED (-7) /* valid request the build does not support          */
 #define PA_EINTERNAL (-8)    /* internal invariant violated                       */
+#define PA_EIO (-9)          /* file cannot be read or written, or is corrupt     */
 
 #define PA_METRIC_L2 0
 #define PA_METRIC_IP 1
@@ -307,6 +308,41 @@ pa_status pa_index_build_entries(pa_index* idx, const int32_t* pivot_ids_host, i
  * centroids_host [r][d_r]; any pointer may be NULL. */
 pa_status pa_index_get_state(const pa_index* idx, float* V_host, int32_t* buckets_host,
                              float* centroids_host);
+
+/* Checkpoint of the built index (the state sections 4.1 and 5 build offline: the
+ * projection V, the reduced vectors X_r as stored, the packed subgraph, and the entry
+ * table with its centroids and bucket ids).  The caller-owned inputs (X and the full
+ * graph) are not written: they are the data, not the index.
+ *
+ * pa_index_save writes `path` (created or truncated): a fixed header (magic, format
+ * version, dim, d_r, metric, X_r dtype, r, pivot dtype, N, subgraph degree, pivots per
+ * bucket) and its FNV-1a 64-bit checksum, then sections, each with its byte length and
+ * checksum.  Host byte order.
+ * PA_ESTATE unless projection, subgraph and entries are built; PA_EIO on a write error.
+ *
+ * pa_index_load reads such a file into an index created with the same parameters (dim,
+ * d_r, metric, xr_dtype, r, pivot_dtype) after pa_index_set_data with the same N; it
+ * replaces any projection, subgraph and entries the index held and leaves it ready to
+ * search.  PA_EIO if the file cannot be read, is truncated or fails a checksum (or
+ * holds an id out of range); PA_EINVAL if its header disagrees with the index;
+ * PA_ESTATE before set_data.  The file is read and verified completely before the index
+ * is touched, so these failures leave the index unchanged; a device allocation or copy
+ * failure after that (PA_EHBM, PA_EHIP) leaves it with no projection, subgraph or
+ * entries. */
+pa_status pa_index_save(const pa_index* idx, const char* path);
+pa_status pa_index_load(pa_index* idx, const char* path);
+
+/* Sizes and build state of an index. */
+typedef struct {
+    int64_t N;           /* nodes (0 before set_data)                           */
+    int32_t R_full;      /* padded full-graph degree                            */
+    int32_t R_sub;       /* padded subgraph degree (0 before the subgraph)      */
+    int32_t n_pivots;    /* entry pivots, r buckets of n_pivots / r (0 before)  */
+    int32_t built;       /* bit 0 data, bit 1 projection, bit 2 subgraph, bit 3 entries */
+    int64_t hbm_bytes;   /* device bytes the index holds, work buffers included */
+} pa_index_info;
+
+pa_status pa_index_get_info(const pa_index* idx, pa_index_info* out);
 
 /* Device pointers of the index's tables (for stage-isolated calls); any may be NULL. */
 pa_status pa_index_device_tables(const pa_index* idx, const void** Xr_dev,

@@ -57,6 +57,11 @@ class SearchStats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class IndexInfo(C.Structure):
+    _fields_ = [("N", C.c_int64), ("R_full", C.c_int32), ("R_sub", C.c_int32), ("n_pivots", C.c_int32),
+                ("built", C.c_int32), ("hbm_bytes", C.c_int64)]
+
+
 class ServerParams(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_batch", C.c_int32), ("streams", C.c_int32),
                 ("threads", C.c_int32), ("max_k", C.c_int32)]
@@ -97,6 +102,9 @@ _SIGS = {
     "pa_index_build_subgraph": [_P, _P, _P, _P],
     "pa_index_build_entries": [_P, _P, _I32, _P, _I32],
     "pa_index_get_state": [_P, _P, _P, _P],
+    "pa_index_get_info": [_P, C.POINTER(IndexInfo)],
+    "pa_index_save": [_P, C.c_char_p],
+    "pa_index_load": [_P, C.c_char_p],
     "pa_index_device_tables": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                                C.POINTER(_P), C.POINTER(_P)],
     "pa_search": [_P, _P, _I64, _I32, C.POINTER(SearchOpts), _P, _P, _P, C.POINTER(SearchStats)],
@@ -477,6 +485,20 @@ class Index:
         init, pi = _host(init, np.int32)
         _check(lib().pa_index_build_entries(self._h, pp, pivot_ids.shape[0], pi, iters))
         self.n_p = pivot_ids.shape[0]
+
+    def info(self):
+        inf = IndexInfo()
+        _check(lib().pa_index_get_info(self._h, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in inf._fields_}
+
+    def save(self, path: str):
+        """Write the built index (projection, reduced vectors, subgraph, entry table) to path."""
+        _check(lib().pa_index_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Replace projection, subgraph and entries with a checkpoint written by save()."""
+        _check(lib().pa_index_load(self._h, os.fsencode(path)))
+        self.n_p = self.info()["n_pivots"]
 
     def projection(self):
         V = np.empty((self.cfg.dim, self.cfg.d_r), dtype=np.float32)

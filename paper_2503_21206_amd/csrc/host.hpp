@@ -43,20 +43,26 @@ int host_core_count();
 using DistFn = float (*)(const double*, const float*, int);
 DistFn pick_distance(int metric);
 
-// Per-thread visited table: epoch-stamped marks over N nodes.
+// Per-thread visited table: one bit per node (N/8 bytes, small enough to stay in a core's
+// L2 at N = 1M) and the list of words a query touched, which are cleared when the next
+// query starts.
 class Visited {
 public:
     void reset(int64_t n);
     void next_epoch();
     bool test_and_set(int32_t v) {
-        if (mark_[v] == epoch_) return true;
-        mark_[v] = epoch_;
+        const size_t w = static_cast<uint32_t>(v) >> 6;
+        const uint64_t bit = uint64_t{1} << (v & 63);
+        const uint64_t b = bits_[w];
+        if (b & bit) return true;
+        if (b == 0) touched_.push_back(static_cast<uint32_t>(w));
+        bits_[w] = b | bit;
         return false;
     }
 
 private:
-    std::vector<uint32_t> mark_;
-    uint32_t epoch_ = 0;
+    std::vector<uint64_t> bits_;
+    std::vector<uint32_t> touched_;
 };
 
 // One candidate of the host-side list C.

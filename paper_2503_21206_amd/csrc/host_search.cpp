@@ -274,16 +274,14 @@ DistFn pick_distance(int metric) {
 }
 
 void Visited::reset(int64_t n) {
-    mark_.assign(static_cast<size_t>(n), 0u);
-    epoch_ = 0;
+    bits_.assign(static_cast<size_t>((n + 63) / 64), 0);
+    touched_.clear();
+    touched_.reserve(4096);
 }
 
 void Visited::next_epoch() {
-    ++epoch_;
-    if (epoch_ == 0) {
-        std::fill(mark_.begin(), mark_.end(), 0u);
-        epoch_ = 1;
-    }
+    for (uint32_t w : touched_) bits_[w] = 0;
+    touched_.clear();
 }
 
 void host_stages_one(const StageContext& ctx, const float* qf, const int32_t* beam, int n_beam, int ef_cpu,
