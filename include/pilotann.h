@@ -354,7 +354,7 @@ typedef struct {
     int32_t ef_gpu;       /* stage-1 list size (1..PA_MAX_EF)                     */
     int32_t ef_cpu;       /* stage-2/3 list size                                   */
     int32_t E;            /* entries per query (0: min(ef_gpu, n_p / r))           */
-    int32_t batch;        /* queries per pipelined sub-batch (0: automatic)        */
+    int32_t batch;        /* queries per pipelined sub-batch (0: 16,384)           */
     int32_t stage_mask;   /* bit 0 GPU stage, bit 1 refinement (0: both)           */
     int32_t cache_log2;   /* GPU visited-cache size (0: automatic)                 */
     int32_t threads;      /* host threads (0: index default)                       */

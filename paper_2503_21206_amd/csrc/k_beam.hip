@@ -222,6 +222,7 @@ struct Wave {
         stored = false;
         if (v < 0) return false;
         uint32_t h = hash_slot(static_cast<uint32_t>(v), a.hlog);
+#pragma nounroll
         for (int p = 0; p < kProbes; ++p) {
             const uint32_t old = atomicCAS(&cache[h], kEmpty, static_cast<uint32_t>(v));
             if (old == kEmpty) {
@@ -370,8 +371,10 @@ struct Wave {
     }
 };
 
+// Small lists (CH <= 2) fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about
+// as many); larger lists keep the compiler's choice rather than spill.
 template <int DT, int MET, int CH>
-__global__ __launch_bounds__(256) void beam_kernel(BeamArgs a) {
+__global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;

@@ -22,6 +22,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kTQ = 16;          // queries per tile (MFMA rows)
 constexpr int kMaxClusters = 64;
 constexpr int kRerankSlack = 16; // FP32 form pre-selects E + 16 pivots for the exact re-score
+constexpr int kWaves = 16;       // one wavefront per query row of a tile: the per-row sorts and
+                                 // re-scores are latency bound, so every row gets its own wave
+constexpr int kThreads = 64 * kWaves;
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
     uint32_t u = __float_as_uint(f);
@@ -145,7 +148,7 @@ __device__ void bitonic_row(uint64_t* s, int n, int lane) {
 }
 
 template <bool FP8>
-__global__ __launch_bounds__(256) void score_kernel(FesArgs a) {
+__global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int d = a.d;
     float* Aq = reinterpret_cast<float*>(smem);          // [kTQ][d]
@@ -180,11 +183,11 @@ __global__ __launch_bounds__(256) void score_kernel(FesArgs a) {
     const int c = s_c;
     if (c < 0) return;
     const int cntq = s_cnt;
-    for (int idx = t; idx < kTQ * d; idx += 256) {
+    for (int idx = t; idx < kTQ * d; idx += kThreads) {
         const int i = idx / d, j = idx - (idx / d) * d;
         Aq[idx] = (i < cntq) ? a.Qr[static_cast<int64_t>(qidx[i]) * d + j] : 0.0f;
     }
-    for (int idx = t; idx < kTQ * P; idx += 256) work[idx] = ~0ull;
+    for (int idx = t; idx < kTQ * P; idx += kThreads) work[idx] = ~0ull;
     __syncthreads();
     if (t < kTQ) {
         float s2 = 0.0f, amax = 0.0f;
@@ -198,14 +201,14 @@ __global__ __launch_bounds__(256) void score_kernel(FesArgs a) {
     }
     __syncthreads();
     if (FP8) {
-        for (int idx = t; idx < kTQ * d; idx += 256) Aq8[idx] = dev_f32_to_e4m3(Aq[idx] / qs[idx / d]);
+        for (int idx = t; idx < kTQ * d; idx += kThreads) Aq8[idx] = dev_f32_to_e4m3(Aq[idx] / qs[idx / d]);
         __syncthreads();
     }
 
     const int64_t cb = static_cast<int64_t>(c) * n_b;
     const int nblk = CH / 16;
     for (int c0 = 0; c0 < n_b; c0 += CH) {
-        for (int pb = w; pb < nblk; pb += 4) {
+        for (int pb = w; pb < nblk; pb += kWaves) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int p = c0 + pb * 16 + (lane & 15);
             const bool pv = p < n_b;
@@ -238,15 +241,15 @@ __global__ __launch_bounds__(256) void score_kernel(FesArgs a) {
             }
         }
         __syncthreads();
-        for (int row = w; row < cntq; row += 4) bitonic_row(work + row * P, P, lane);
+        for (int row = w; row < cntq; row += kWaves) bitonic_row(work + row * P, P, lane);
         __syncthreads();
         // the chunk slots are refilled by the next chunk; the tail past K + CH stays +inf
-        for (int row = w; row < cntq; row += 4)
+        for (int row = w; row < cntq; row += kWaves)
             for (int i = K + lane; i < K + CH; i += 64) work[row * P + i] = ~0ull;
         __syncthreads();
     }
 
-    for (int row = w; row < cntq; row += 4) {
+    for (int row = w; row < cntq; row += kWaves) {
         uint64_t* s = work + row * P;
         // re-score the K pre-selected pivots in the direct form, keys by node id
         for (int j = lane; j < P; j += 64) {
@@ -316,8 +319,8 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     PA_HIP(hipGetLastError());
     FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, CH, P, metric, scratch_i32, ids, dists};
     const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
-    if (fp8) hipLaunchKernelGGL(score_kernel<true>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
-    else hipLaunchKernelGGL(score_kernel<false>, dim3(max_tiles), dim3(256), lds_for(P), s, a);
+    if (fp8) hipLaunchKernelGGL(score_kernel<true>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
+    else hipLaunchKernelGGL(score_kernel<false>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
     PA_HIP(hipGetLastError());
 }
 
