@@ -201,6 +201,73 @@ def cpu_only(idx, spec, fx, target, steps):
             "curve": curve}
 
 
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "fp8": 5000.0}
+
+
+def gemm_leg(spec, fx, V, reps=20):
+    """The MFMA kernels on their own, timed with HIP events on the stream they run on:
+    the query projection and the FES pivot scoring at the bench shape (fp32), and the FES
+    at the 768-d inner-product shape of the large configuration (d_r = 128, 65,536 FP8
+    pivots in 32 buckets, E = 64, K = 256).  Algorithmic FLOPs: 2*m*D*d_r for the
+    projection and 2*m*(n_p/r)*d_r for the pivot product (Table 2, FES general); the
+    pre-selection sort and the exact re-score are extra work on top."""
+    import torch
+    import paper_2503_21206_amd as pa
+    from synth.data import make_rng
+    dev = torch.device("cuda")
+    rng = make_rng(spec.seed, 90)
+    out = {}
+
+    def timed_call(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    m = spec.queries
+    Q = torch.as_tensor(fx["Q"]).to(dev)
+    Vt = torch.as_tensor(V).to(dev)
+    ms = timed_call(lambda: pa.project(Q, Vt, "f32"))
+    fl = 2.0 * m * spec.dim * spec.d_r
+    out["projection"] = {"shape": f"{m} x {spec.dim} -> {spec.d_r}", "ms": round(ms, 4),
+                         "tflops": round(fl / ms / 1e9, 2), "peak": MFMA_PEAK_TFLOPS["f32"],
+                         "frac": round(fl / ms / 1e9 / MFMA_PEAK_TFLOPS["f32"], 4), "dtype": "f32"}
+
+    def fes_case(name, m, d, r, n_b, E, K, dtype, metric):
+        Qr = torch.as_tensor(rng.standard_normal((m, d)).astype(np.float32)).to(dev)
+        EV = rng.standard_normal((r, n_b, d)).astype(np.float32)
+        EVn = torch.as_tensor((EV.astype(np.float64) ** 2).sum(-1).astype(np.float32)).to(dev)
+        EVid = torch.as_tensor(np.arange(r * n_b, dtype=np.int32).reshape(r, n_b)).to(dev)
+        cl = torch.as_tensor(rng.integers(0, r, m).astype(np.int32)).to(dev)
+        EVd = torch.as_tensor(EV).to(dev)
+        if dtype == "fp8":
+            codes, scales = pa.quantize_fp8_rows(EV.reshape(-1, d))
+            E8 = torch.as_tensor(codes.reshape(r, n_b, d)).to(dev)
+            Es = torch.as_tensor(scales.reshape(r, n_b)).to(dev)
+            fn = lambda: pa.select_entries_fp8(Qr, cl, EVd, E8, Es, EVn, EVid, E, K, metric)
+        else:
+            fn = lambda: pa.select_entries(Qr, cl, EVd, EVn, EVid, E, metric)
+        ms = timed_call(fn)
+        fl = 2.0 * m * n_b * d
+        out[name] = {"shape": f"{m} queries x {r} buckets of {n_b} pivots x {d} dims, E={E}"
+                              + (f", K={K}" if dtype == "fp8" else ""),
+                     "ms": round(ms, 4), "tflops": round(fl / ms / 1e9, 2), "peak": MFMA_PEAK_TFLOPS[dtype],
+                     "frac": round(fl / ms / 1e9 / MFMA_PEAK_TFLOPS[dtype], 5), "dtype": dtype}
+
+    for args in (("fes_f32", m, spec.d_r, spec.r, spec.n_pivots // spec.r, 64, 0, "f32", spec.metric),
+                 ("fes_fp8_768d", m, 128, 32, 65536 // 32, 64, 256, "fp8", "ip")):
+        try:
+            fes_case(*args)
+        except pa.PilotannError as e:  # a shape this device cannot hold is reported, not fatal
+            out[args[0]] = {"error": str(e)}
+    return out
+
+
 def roofline(spec, agg, steps, ef, E, xr_bytes, form):
     """Beam-kernel bytes and time per launch; ef is the stage-1 list size."""
     m = spec.queries * steps
@@ -309,6 +376,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-only", action="store_true", help="skip the GPU-stage-off comparison leg")
+    ap.add_argument("--no-gemm", action="store_true", help="skip the MFMA kernel leg")
     ap.add_argument("--forms", default="f32,f16")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -387,6 +455,9 @@ def main():
         "roofline": f["roofline"],
         "forms": forms,
     }
+    if not args.no_gemm:
+        log("MFMA kernels on their own")
+        out["gemm"] = gemm_leg(spec, fx, shared["V"])
     if baseline_cpu_only is not None:
         co = dict(baseline_cpu_only)
         co["what"] = ("this library with the GPU stage off: Algorithm 1 on the full graph on the host cores from "
