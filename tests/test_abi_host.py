@@ -150,10 +150,6 @@ def tiny():
                 sub_adj=oracle.padded_from_csr(sr, sn, 32))
 
 
-def _near_tie_ok(ids, ref_ids, margin, thr=2e-5):
-    return (ids == ref_ids).all() or margin < thr
-
-
 def test_cpu_stages_match_oracle(tiny):
     X, Q = tiny["X"], tiny["Q"]
     rng = make_rng(11, 0)
