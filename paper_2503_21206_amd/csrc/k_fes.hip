@@ -79,18 +79,19 @@ __global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------- pivot scoring
-// Any bucket size.  The bucket is scanned in chunks of CH pivots; each query row keeps its
-// best K keys in the first K slots of an LDS work row of P (a power of two >= K + CH)
-// keys, the chunk's keys land in the next CH slots, and the owning wave re-sorts the row
-// (bitonic).  The chunk is scored on MFMA into an approximate distance in the expanded
-// form |q|^2 + |p|^2 - 2 q.p (FP32 form: v_mfma_f32_16x16x4f32; FP8 form: queries encoded
-// per row like the pivots, scale = max|q| / 448, e4m3 round to nearest even, then
-// v_mfma_f32_16x16x32_fp8_fp8).  Pre-selection keys carry the pivot's index in its bucket.
-// The K pre-selected pivots are then re-scored in the direct form with float-float
-// arithmetic, so the emitted distances are the correctly rounded fp32 ones, and the top E
-// by (distance, node id) is emitted.  FP32 form: K = E + 16, so an exact top-E member is
-// lost only if more than 16 pivots fall within the expanded form's rounding error of it;
-// FP8 form: K is a multiple of E that absorbs the e4m3 error.
+// Any bucket size.  Each query row keeps a running list of its best K2 = next_pow2(K)
+// keys (ascending) in LDS.  The bucket is scanned in chunks of K2 pivots, scored on MFMA
+// into an approximate distance in the expanded form |q|^2 + |p|^2 - 2 q.p (FP32 form:
+// v_mfma_f32_16x16x4f32; FP8 form: queries encoded per row like the pivots, scale =
+// max|q| / 448, e4m3 round to nearest even, then v_mfma_f32_16x16x32_fp8_fp8); the
+// row's wavefront sorts the chunk descending, keeps the elementwise smaller of list and
+// chunk (the lower half of a bitonic merge) and merges it back into ascending order.
+// Pre-selection keys carry the pivot's index in its bucket.  The K pre-selected pivots
+// are then re-scored in the direct form with float-float arithmetic, so the emitted
+// distances are the correctly rounded fp32 ones, and the top E by (distance, node id) is
+// emitted.  FP32 form: K = E + 16, so an exact top-E member is lost only if more than 16
+// pivots fall within the expanded form's rounding error of it; FP8 form: K is a multiple
+// of E that absorbs the e4m3 error.
 typedef long fp8x8 __attribute__((ext_vector_type(1)));
 
 __device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
@@ -122,20 +123,21 @@ struct FesArgs {
     const float* EVscale;
     const float* EVnorm;
     const int32_t* EVid;
-    int r, n_b, E, K, CH, P, metric;
+    int r, n_b, E, K, K2, CH, P, metric;  // K2 = next power of two >= K
     const int32_t* scratch;
     int32_t* out_ids;
     float* out_d;
 };
 
-__device__ void bitonic_row(uint64_t* s, int n, int lane) {
+// Bitonic sort of s[0, n) (n a power of two) by one wavefront, ascending or descending.
+__device__ void bitonic_sort(uint64_t* s, int n, int lane, bool descending) {
     for (int k = 2; k <= n; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = lane; i < n; i += 64) {
                 const int l = i ^ j;
                 if (l > i) {
                     const uint64_t x = s[i], y = s[l];
-                    const bool up = (i & k) == 0;
+                    const bool up = ((i & k) == 0) != descending;
                     if ((x > y) == up) {
                         s[i] = y;
                         s[l] = x;
@@ -145,6 +147,29 @@ __device__ void bitonic_row(uint64_t* s, int n, int lane) {
             wave_sync();
         }
     }
+}
+
+// Ascending order of a bitonic sequence s[0, n) (n a power of two).
+__device__ void bitonic_merge(uint64_t* s, int n, int lane) {
+    for (int j = n >> 1; j > 0; j >>= 1) {
+        for (int i = lane; i < n; i += 64) {
+            const int l = i ^ j;
+            if (l > i) {
+                const uint64_t x = s[i], y = s[l];
+                if (x > y) {
+                    s[i] = y;
+                    s[l] = x;
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
 template <bool FP8>
@@ -160,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     __shared__ int s_c, s_cnt;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int r = a.r, n_b = a.n_b, K = a.K, CH = a.CH, P = a.P;
+    const int r = a.r, n_b = a.n_b, K = a.K, K2 = a.K2, CH = a.CH, P = a.P;
     const int32_t* counts = a.scratch;
     const int32_t* offsets = a.scratch + r;
     const int32_t* tprefix = a.scratch + 2 * r + 1;
@@ -221,10 +246,22 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
                 }
             } else {
-                for (int k = 0; k < d; k += 4) {
-                    const float av = Aq[(lane & 15) * d + k + (lane >> 4)];
-                    const float bv = pv ? a.EV[(cb + p) * d + k + (lane >> 4)] : 0.0f;
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                // B operand of 16 k-steps loaded before the MFMA chain that consumes it
+                for (int k0 = 0; k0 < d; k0 += 64) {
+                    float bv[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int k = k0 + 4 * i;
+                        bv[i] = (pv && k < d) ? a.EV[(cb + p) * d + k + (lane >> 4)] : 0.0f;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int k = k0 + 4 * i;
+                        if (k < d) {
+                            const float av = Aq[(lane & 15) * d + k + (lane >> 4)];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[i], acc, 0, 0, 0);
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -237,41 +274,75 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                                                                   : -dot;
                     key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(p);
                 }
-                work[row * P + K + pb * 16 + (lane & 15)] = key;
+                work[row * P + CH + pb * 16 + (lane & 15)] = key;
             }
         }
         __syncthreads();
-        for (int row = w; row < cntq; row += kWaves) bitonic_row(work + row * P, P, lane);
-        __syncthreads();
-        // the chunk slots are refilled by the next chunk; the tail past K + CH stays +inf
-        for (int row = w; row < cntq; row += kWaves)
-            for (int i = K + lane; i < K + CH; i += 64) work[row * P + i] = ~0ull;
+        // fold the chunk into the row's running list s[0, CH) (ascending): sort the chunk
+        // descending, keep the smaller of s[i] and chunk[i] (the lower half of a bitonic
+        // merge: the CH smallest of both, as a bitonic sequence), merge that ascending
+        for (int row = w; row < cntq; row += kWaves) {
+            uint64_t* srow = work + row * P;
+            bitonic_sort(srow + CH, CH, lane, true);
+            for (int i = lane; i < CH; i += 64) {
+                const uint64_t x = srow[i], y = srow[CH + i];
+                srow[i] = x < y ? x : y;
+            }
+            wave_sync();
+            bitonic_merge(srow, CH, lane);
+        }
         __syncthreads();
     }
 
     for (int row = w; row < cntq; row += kWaves) {
         uint64_t* s = work + row * P;
-        // re-score the K pre-selected pivots in the direct form, keys by node id
-        for (int j = lane; j < P; j += 64) {
-            uint64_t key = ~0ull;
-            if (j < K && s[j] != ~0ull) {
-                const int p = static_cast<int>(s[j] & 0xFFFFFFFFu);
-                const float* pv = a.EV + (cb + p) * d;
-                const float* qv = Aq + row * d;
-                ff32 acc{0.0f, 0.0f};
-                if (a.metric == PA_METRIC_L2) {
-                    for (int k = 0; k < d; ++k) ff_add_sqdiff(acc, qv[k], pv[k]);
-                } else {
-                    for (int k = 0; k < d; ++k) ff_add_prod(acc, qv[k], pv[k]);
+        // re-score the K pre-selected pivots in the direct form, keys by node id: four
+        // lanes per pivot, each over a quarter of the dimensions in float-float, combined
+        // symmetrically across the quad (so the value is the correctly rounded distance)
+        const float* qv = Aq + row * d;
+        const int per = d / 4;
+        const int sub = lane & 3;
+        for (int base = 0; base < K; base += 16) {
+            const int j = base + (lane >> 2);
+            const bool live = j < K && s[j] != ~0ull;
+            const int p = live ? static_cast<int>(s[j] & 0xFFFFFFFFu) : 0;
+            const int k0 = sub * per;  // d is a multiple of 16: per is a multiple of 4
+            const float4* pv = reinterpret_cast<const float4*>(a.EV + (cb + p) * d + k0);
+            ff32 acc{0.0f, 0.0f};
+            // the lane's quarter of the row in pieces of up to 32 floats, every load of a
+            // piece issued before its arithmetic
+            for (int seg = 0; seg < per; seg += 32) {
+                const int n4 = min(32, per - seg) / 4;
+                float4 x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = (live && u < n4) ? pv[seg / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (u < n4) {
+                        const float* q4 = qv + k0 + seg + 4 * u;
+                        const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            if (a.metric == PA_METRIC_L2) ff_add_sqdiff(acc, q4[c], xv[c]);
+                            else ff_add_prod(acc, q4[c], xv[c]);
+                        }
+                    }
                 }
-                const float v = ff_norm(acc).hi;
-                const float dist = (a.metric == PA_METRIC_L2) ? v : -v;
-                key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
             }
-            s[j] = key;
+            acc = ff_add(acc, ff32{dpp<0xB1>(acc.hi), dpp<0xB1>(acc.lo)});  // lane ^ 1
+            acc = ff_add(acc, ff32{dpp<0x4E>(acc.hi), dpp<0x4E>(acc.lo)});  // lane ^ 2
+            if (sub == 0 && j < K) {
+                uint64_t key = ~0ull;
+                if (live) {
+                    const float dist = (a.metric == PA_METRIC_L2) ? acc.hi : -acc.hi;
+                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
+                }
+                s[j] = key;
+            }
         }
+        for (int j = K + lane; j < K2; j += 64) s[j] = ~0ull;
         wave_sync();
-        bitonic_row(s, P, lane);
+        bitonic_sort(s, K2, lane, false);
         const int64_t q = qidx[row];
         for (int e = lane; e < a.E; e += 64) {
             int32_t id = -1;
@@ -307,17 +378,14 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
         return sizeof(float) * (kTQ * d + 2 * kTQ) + static_cast<size_t>((kTQ * d + 15) / 16) * 16 +
                sizeof(uint64_t) * static_cast<size_t>(kTQ) * P;
     };
-    int CH = 128, P = 0;
-    for (;;) {
-        P = 1;
-        while (P < K + CH) P <<= 1;
-        if (lds_for(P) <= static_cast<size_t>(max_lds) || CH == 16) break;
-        CH >>= 1;
-    }
+    // running list of K2 = next_pow2(K) keys per query row, and chunks of the same size
+    int K2 = 16;
+    while (K2 < K) K2 <<= 1;
+    const int CH = K2, P = 2 * K2;
     require(lds_for(P) <= static_cast<size_t>(max_lds), "FES pre-selection list does not fit in LDS", PA_EUNSUPPORTED);
     hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
     PA_HIP(hipGetLastError());
-    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, CH, P, metric, scratch_i32, ids, dists};
+    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, K2, CH, P, metric, scratch_i32, ids, dists};
     const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
     if (fp8) hipLaunchKernelGGL(score_kernel<true>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
     else hipLaunchKernelGGL(score_kernel<false>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
