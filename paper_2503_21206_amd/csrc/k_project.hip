@@ -94,8 +94,9 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------- routing
-// One wave per query: lane c < r scores centroid c with a sequential fp32 sum of squared
-// differences; the wave takes the minimum (ties to the lowest c).
+// One wave per query: lane c < r scores centroid c with a float-float sum of squared
+// differences (the correctly rounded fp32 distance); the wave takes the minimum (ties to
+// the lowest c).
 __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Qr, int64_t m, int d_r,
                                                     const float* __restrict__ C, int r,
                                                     int32_t* __restrict__ cluster) {
@@ -105,9 +106,27 @@ __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Qr
     const float* qv = Qr + q * d_r;
     float best = __builtin_huge_valf();
     if (lane < r) {
-        const float* cv = C + static_cast<int64_t>(lane) * d_r;
+        // d_r is a multiple of 16: the rows are read as float4, 32 floats at a time, every
+        // load of a piece issued before its arithmetic
+        const float4* cv = reinterpret_cast<const float4*>(C + static_cast<int64_t>(lane) * d_r);
+        const float4* q4 = reinterpret_cast<const float4*>(qv);
         ff32 s{0.0f, 0.0f};
-        for (int j = 0; j < d_r; ++j) ff_add_sqdiff(s, qv[j], cv[j]);
+        for (int seg = 0; seg < d_r / 4; seg += 8) {
+            float4 c[8], x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = seg + u < d_r / 4;
+                c[u] = in ? cv[seg + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                x[u] = in ? q4[seg + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ff_add_sqdiff(s, x[u].x, c[u].x);
+                ff_add_sqdiff(s, x[u].y, c[u].y);
+                ff_add_sqdiff(s, x[u].z, c[u].z);
+                ff_add_sqdiff(s, x[u].w, c[u].w);
+            }
+        }
         best = ff_norm(s).hi;  // the correctly rounded fp32 distance
     }
     // (distance, index) minimum across the wave, lowest index on ties
