@@ -201,6 +201,64 @@ def cpu_only(idx, spec, fx, target, steps):
             "curve": curve}
 
 
+def ablation(idx, spec, fx, ef, steps=2):
+    """The pipeline with parts switched off at the chosen (ef_gpu, ef_cpu), in the spirit of
+    the paper's ablation: no refinement (stage 1 candidates go straight to stage 3), no
+    GPU stage (stage 3 alone from the FES entries), and GPU/host overlap across sub-batches
+    (five sub-batches of 2,048 queries) against one launch."""
+    import torch
+    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
+    cases = {"full": {}, "no_refinement": {"stage_mask": 1}, "no_gpu_stage": {"stage_mask": 2},
+             "overlapped_sub_batches_2048": {"batch": 2048}}
+    out = {}
+    for name, kw in cases.items():
+        idx.search(fx["Q"], spec.k, ef[0], ef[1], Q_dev=Qd, **kw)
+        t0 = time.perf_counter()
+        n2 = n3 = 0
+        for _ in range(steps):
+            ids, _, cnt, st = idx.search(fx["Q"], spec.k, ef[0], ef[1], Q_dev=Qd, with_counters=True, **kw)
+            n2 += int(cnt[:, 3].sum())
+            n3 += int(cnt[:, 4].sum())
+        dt = time.perf_counter() - t0
+        m = spec.queries * steps
+        out[name] = {"qps": round(spec.queries * steps / dt, 1), "recall": round(recall(ids, fx["gt"], spec.k), 5),
+                     "host_distances_per_query": round((n2 + n3) / m, 1)}
+        log(f"  ablation {name}: {out[name]}")
+    return out
+
+
+def top100(idx, spec, fx, target, steps=2):
+    """k = 100: the fastest (ef_gpu, ef_cpu) with recall@100 >= target (ef >= k)."""
+    import torch
+    from synth.knn import exact_knn
+    gt100, _ = exact_knn(fx["X"], fx["Q"], 100, spec.metric, device="cuda")
+    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
+    curve, best = [], None
+    for ef_cpu in (100, 128, 160, 192, 256, 384, 512):
+        hit = []
+        for ef_gpu in sorted({ef_cpu, min(512, 2 * ef_cpu)}):
+            idx.search(fx["Q"][:1000], 100, ef_gpu, ef_cpu, Q_dev=Qd[:1000])
+            ids, _, _, st = idx.search(fx["Q"], 100, ef_gpu, ef_cpu, Q_dev=Qd)
+            rec = recall(ids, gt100, 100)
+            qps = fx["Q"].shape[0] / (st["wall_ms"] / 1e3)
+            curve.append({"ef_gpu": ef_gpu, "ef_cpu": ef_cpu, "recall": round(rec, 5), "qps": round(qps, 1)})
+            log(f"  k=100 ef_gpu={ef_gpu} ef_cpu={ef_cpu} recall@100={rec:.4f} qps={qps:,.0f}")
+            if rec >= target:
+                hit.append((qps, ef_gpu, ef_cpu))
+        if hit:
+            best = max(hit)
+            break
+    if best is None:
+        return {"value": None, "curve": curve}
+    _, ef_gpu, ef_cpu = best
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ids, _, _, _ = idx.search(fx["Q"], 100, ef_gpu, ef_cpu, Q_dev=Qd)
+    dt = time.perf_counter() - t0
+    return {"value": round(spec.queries * steps / dt, 1), "unit": "queries/s", "metric": "recall@100",
+            "ef_gpu": ef_gpu, "ef_cpu": ef_cpu, "recall": round(recall(ids, gt100, 100), 5), "curve": curve}
+
+
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "fp8": 5000.0}
 
 
@@ -377,6 +435,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cpu-only", action="store_true", help="skip the GPU-stage-off comparison leg")
     ap.add_argument("--no-gemm", action="store_true", help="skip the MFMA kernel leg")
+    ap.add_argument("--no-extra", action="store_true", help="skip the ablation and top-100 legs")
     ap.add_argument("--forms", default="f32,f16")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -403,6 +462,7 @@ def main():
     forms = {}
     serving = None
     baseline_cpu_only = None
+    extra = {}
     for form in args.forms.split(","):
         idx = build_index(spec, fx, form, shared)
         if args.ef:
@@ -435,6 +495,11 @@ def main():
         if form == "f32" and not args.no_cpu_only:
             log("cpu-only (GPU stage off)")
             baseline_cpu_only = cpu_only(idx, spec, fx, args.target, max(1, min(args.steps, 3)))
+        if form == "f32" and not args.no_extra:
+            log("ablation")
+            extra["ablation"] = ablation(idx, spec, fx, ef)
+            log("top-100")
+            extra["top100"] = top100(idx, spec, fx, args.target)
         if form == "f16" and args.serve_rates:
             rates = [float(x) for x in args.serve_rates.split(",") if x]
             serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
@@ -455,6 +520,7 @@ def main():
         "roofline": f["roofline"],
         "forms": forms,
     }
+    out.update(extra)
     if not args.no_gemm:
         log("MFMA kernels on their own")
         out["gemm"] = gemm_leg(spec, fx, shared["V"])
