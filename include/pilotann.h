@@ -202,7 +202,7 @@ pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev,
  * distance-evaluation count equals |visited| when no forget event happened; counters[i][3] is a
  * termination-guard flag (0).  1 <= ef <= PA_MAX_EF,
  * 1 <= R <= PA_MAX_DEGREE.  cache_log2 selects the per-query LDS visited-cache size
- * (2^cache_log2 entries, 8..13; 0 = automatic).  Xr_dev must hold N rows.
+ * (2^cache_log2 entries, 8..13; 0 = automatic).  Xr_dev must hold N rows, N <= 2^30.
  * counters_dev[i][3] is 1 if the query stopped at the N-expansion guard (never expected). */
 pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
                           int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,

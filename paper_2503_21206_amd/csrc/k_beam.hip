@@ -3,8 +3,8 @@
 //
 // Per wavefront:
 //   c[CH] (VGPRs)  the candidate list C, sorted ascending by the 64-bit key
-//                  (orderable(distance) << 32) | (id << 1) | checked; entry t lives in
-//                  lane t % 64 of register t / 64; slots at or beyond |C| hold +inf
+//                  (orderable(distance) << 32) | (id << 2) | inexact << 1 | checked; entry t
+//                  lives in lane t % 64 of register t / 64; slots at or beyond |C| hold +inf
 //   LDS            a scatter area for merges, a 64-slot staging area for the current batch
 //                  of neighbours, and an open-addressing visited cache of node ids
 //
@@ -13,22 +13,33 @@
 // reproduces Algorithm 1 with an exact visited set while holding only a bounded cache:
 // the cache never reports an unvisited node as visited (it stores full ids), it may only
 // forget nodes.  A forgotten node v that is met again is scored again; if v is still in
-// C its key is bit-identical (the distance does not depend on lane placement) and the
-// duplicate is dropped during the merge, and if v had left C then C was full and its
-// ef-th key has only decreased since, so v is rejected again.  Either way C evolves
-// exactly as in Algorithm 1; only the count of distance evaluations can exceed |visited|
-// (reported per query together with the number of forget events).
+// C the duplicate is recognised by its id and dropped, and if v had left C then C was
+// full and its ef-th key has only decreased since, so v is rejected again.  Either way C
+// evolves exactly as in Algorithm 1; only the count of distance evaluations can exceed
+// |visited| (reported per query together with the number of forget events).
+//
+// Distances (L2).  Every decision must follow the exact distance rounded once to fp32.
+// A plain fp32 sum of 16 fused squares per lane plus the lane reduction lies within a
+// few dozen units of the orderable encoding of the correctly rounded exact distance, so
+// each new candidate is first scored that way (its key flagged inexact).  Two keys whose
+// encodings are farther apart than twice that radius are ordered as their exact values,
+// which decides nearly every comparison (the ef-th-key filter, the position in C, the
+// order among the new candidates).  When some comparison involves closer keys, the
+// batch's candidates and the inexact entries of C are re-scored exactly (float-float:
+// the correctly rounded value, which any summation order also rounds to) and that step
+// is decided on exact keys; the entries left in C are re-scored exactly at the end,
+// before the output.  A re-scored key stays within the radius of its plain value, so C
+// stays sorted and every decision equals the exact one.  Inner products have no
+// relative bound of this kind and are scored exactly at once.
 //
 // One loop step: find the first unchecked entry of C (one ballot per register), mark it
 // checked, take its adjacency row (one coalesced load of R ids, issued one step early for
 // the entry that was next in line when it still is), test-and-set the ids in the cache,
 // gather the reduced vectors of the new ids (GS lanes per vector, 16 elements per lane,
 // all loads of a round in flight together), reduce each distance across its GS lanes
-// with DPP butterflies in float-float arithmetic (so the fp32 distance is the correctly
-// rounded exact one, which any other summation order also rounds to), drop candidates
-// not better than C[ef-1] or already in C, rank the survivors against C and against
-// each other with ballots, and apply the merge as one scatter to LDS and one gather back
-// into the registers.
+// with DPP butterflies, drop candidates not better than C[ef-1] or already in C, rank
+// the survivors against C and against each other with ballots, and apply the merge as
+// one scatter to LDS and one gather back into the registers.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -51,9 +62,27 @@ __device__ __forceinline__ uint32_t ord_f32(float f) {
 __device__ __forceinline__ float unord_f32(uint32_t u) {
     return __uint_as_float((u & 0x80000000u) ? (u ^ 0x80000000u) : ~u);
 }
+constexpr uint64_t kChecked = 1;
+constexpr uint64_t kInexact = 2;
+constexpr uint64_t kFlags = 3;
 __device__ __forceinline__ uint64_t make_key(float d, uint32_t id) {
-    return (static_cast<uint64_t>(ord_f32(d)) << 32) | (static_cast<uint64_t>(id) << 1);
+    return (static_cast<uint64_t>(ord_f32(d)) << 32) | (static_cast<uint64_t>(id) << 2);
 }
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return static_cast<uint32_t>(k) >> 2; }
+
+// A plain fp32 squared distance s (16 fused squares per lane, then the lane reduction) is
+// within 2^-19.4 (relative) of the exact one: each term, all of them non-negative, meets
+// at most 24 roundings of 2^-24.  In the orderable encoding that is at most 49 units
+// between s and the correctly rounded exact value (24.3 ulps of s's binade, twice as many
+// units in the binade below, plus the final rounding); kNear adds a margin.  Keys whose
+// encodings differ by more than 2 kNear are therefore ordered as their exact values.
+constexpr uint32_t kNear = 80;
+// Plain values outside [2^-60, 2^60] (where the relative bound may fail) and non-finite
+// ones are never used for a decision: orderable encodings of 2^-60 and 2^60.
+constexpr uint32_t kOrdLo = 0x80000000u | (67u << 23);
+constexpr uint32_t kOrdHi = 0x80000000u | (187u << 23);
+__device__ __forceinline__ bool near(uint32_t a, uint32_t b) { return a - b + 2 * kNear <= 4 * kNear; }
+__device__ __forceinline__ uint32_t hi32(uint64_t k) { return static_cast<uint32_t>(k >> 32); }
 __device__ __forceinline__ int mbcnt(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
@@ -94,6 +123,17 @@ __device__ __forceinline__ float group_sum(ff32 s, int gs) {
     if (gs >= 64) s = ff_add(s, shfl_xor(s, 32));
     if (gs == 1) s = ff_norm(s);
     return s.hi;
+}
+// Plain fp32 sum over aligned groups of gs lanes (same pairing; every lane of a group ends
+// with the same bits).
+__device__ __forceinline__ float group_sum_plain(float s, int gs) {
+    if (gs >= 2) s += dpp<0xB1>(s);
+    if (gs >= 4) s += dpp<0x4E>(s);
+    if (gs >= 8) s += dpp<0x141>(s);
+    if (gs >= 16) s += dpp<0x140>(s);
+    if (gs >= 32) s += __shfl_xor(s, 16);
+    if (gs >= 64) s += __shfl_xor(s, 32);
+    return s;
 }
 
 struct BeamArgs {
@@ -169,6 +209,7 @@ struct Wave {
 
     const BeamArgs& a;
     int lane, sub, grp, gs, vpl, hmask;
+    bool ragged;  // gs * KC chunks exceed the row: some lanes hold chunks past its end
     uint64_t c[CH];
     uint64_t* tmp;
     uint64_t* st_key;
@@ -180,6 +221,7 @@ struct Wave {
     int n_dist = 0;
     int fill = 0;
     int forgot = 0;
+    int n_exact = 0;  // steps decided on exact keys after an undecided interval comparison
 
     __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_, int ef_) : a(args), lane(lane_) {
         ef = ef_;
@@ -188,6 +230,7 @@ struct Wave {
         sub = lane & (gs - 1);
         grp = lane >> a.gs_log;
         hmask = (1 << a.hlog) - 1;
+        ragged = gs * KC > a.cpr;
         tmp = reinterpret_cast<uint64_t*>(base);
         st_key = tmp + CH * 64;
         st_id = reinterpret_cast<uint32_t*>(st_key + 64);
@@ -240,7 +283,7 @@ struct Wave {
 #pragma unroll
         for (int w = 0; w < CH; ++w) {
             const int t = w * 64 + lane;
-            const int v = (t < size) ? static_cast<int>(static_cast<uint32_t>(c[w]) >> 1) : -1;
+            const int v = (t < size) ? static_cast<int>(key_id(c[w])) : -1;
             bool stored;
             test_and_set(v, stored);
             fill += __popcll(__ballot(stored));
@@ -265,6 +308,91 @@ struct Wave {
         return s;
     }
 
+    // Plain fp32 partial of the squared distance over this lane's chunks (16 fused squares).
+    __device__ float lane_plain(const uint4 (&raw)[KC]) const {
+        float s = 0.0f;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            float x[EPC];
+            Chunk<DT>::widen(raw[j], x);
+#pragma unroll
+            for (int e = 0; e < EPC; ++e) {
+                const float d = qv[j][e] - x[e];
+                s = __builtin_fmaf(d, d, s);
+            }
+        }
+        return s;
+    }
+
+    // The key of row id scored by this lane's group (live: the group holds a vector), exact
+    // or plain (then flagged inexact).  Every lane of the group returns the same key.
+    template <bool EXACT>
+    __device__ uint64_t score_row(uint32_t id, bool live) const {
+        const unsigned char* row = a.xr + static_cast<int64_t>(live ? id : 0u) * a.row_bytes;
+        uint4 raw[KC];
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < KC; ++j) {
+                const int ch = min(sub + j * gs, a.cpr - 1);
+                raw[j] = *reinterpret_cast<const uint4*>(row + static_cast<int64_t>(ch) * 16);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KC; ++j) raw[j] = make_uint4(0, 0, 0, 0);
+        }
+        if (ragged) {  // chunks past the row (loaded from its last chunk) are zero
+#pragma unroll
+            for (int j = 0; j < KC; ++j)
+                if (sub + j * gs >= a.cpr) raw[j] = make_uint4(0, 0, 0, 0);
+        }
+        if (EXACT) {
+            const float s = group_sum(lane_partial(raw), gs);
+            return make_key((MET == PA_METRIC_L2) ? s : -s, id);
+        }
+        return make_key(group_sum_plain(lane_plain(raw), gs), id) | kInexact;
+    }
+
+    // Scores the n staged ids into st_key: vpl vectors per round, gs lanes per vector, KC
+    // 16-byte loads per lane (lane sub takes chunks sub, sub + gs, ...: every load
+    // instruction reads gs * 16 contiguous bytes of each of vpl rows), all loads of a round
+    // in flight.
+    template <bool EXACT>
+    __device__ void score_staged(int n) {
+        for (int b0 = 0; b0 < n; b0 += vpl) {
+            const int ci = b0 + grp;
+            const bool live = ci < n;
+            const uint32_t id = live ? st_id[ci] : 0u;
+            const uint64_t k = score_row<EXACT>(id, live);
+            if (sub == 0 && live) st_key[ci] = k;
+        }
+        wave_sync();
+    }
+
+    // Re-scores the inexact entries of C exactly (keys keep their checked flag).
+    __device__ void exactify_list() {
+#pragma unroll
+        for (int w = 0; w < CH; ++w) {
+            const int t = w * 64 + lane;
+            if (t < size) tmp[t] = c[w];
+        }
+        wave_sync();
+        for (int b0 = 0; b0 < size; b0 += vpl) {
+            const int t = b0 + grp;
+            const uint64_t k = (t < size) ? tmp[t] : 0ull;
+            const bool live = t < size && (k & kInexact);
+            if (__ballot(live) == 0) continue;
+            const uint64_t e = score_row<true>(key_id(k), live);
+            if (sub == 0 && live) tmp[t] = e | (k & kChecked);
+        }
+        wave_sync();
+#pragma unroll
+        for (int w = 0; w < CH; ++w) {
+            const int t = w * 64 + lane;
+            if (t < size) c[w] = tmp[t];
+        }
+        wave_sync();
+    }
+
     // Offer one id per lane (-1 = none) to C.  Returns the smallest position at which an
     // entry was inserted (INT_MAX if none).
     __device__ int offer(int v) {
@@ -278,75 +406,112 @@ struct Wave {
         if (fresh) st_id[mbcnt(newmask)] = static_cast<uint32_t>(v);
         wave_sync();
         n_dist += n_new;
-
-        // gather and score vpl vectors per round: gs lanes per vector, KC 16-byte loads per
-        // lane (lane sub takes chunks sub, sub + gs, ...: every load instruction reads
-        // gs * 16 contiguous bytes of each of vpl rows), all loads of a round in flight
-        for (int b0 = 0; b0 < n_new; b0 += vpl) {
-            const int ci = b0 + grp;
-            const bool live = ci < n_new;
-            const unsigned char* row = a.xr + static_cast<int64_t>(live ? st_id[ci] : 0u) * a.row_bytes;
-            uint4 raw[KC];
-#pragma unroll
-            for (int j = 0; j < KC; ++j) {
-                const int ch = sub + j * gs;
-                raw[j] = make_uint4(0, 0, 0, 0);
-                if (live && ch < a.cpr) raw[j] = *reinterpret_cast<const uint4*>(row + static_cast<int64_t>(ch) * 16);
-            }
-            const float s = group_sum(lane_partial(raw), gs);
-            if (sub == 0 && live) st_key[ci] = make_key((MET == PA_METRIC_L2) ? s : -s, st_id[ci]);
+        constexpr bool kLazy = MET == PA_METRIC_L2;
+        score_staged<!kLazy>(n_new);
+        for (int pass = 0;; ++pass) {
+            const int r = place(n_new, !kLazy || pass > 0);
+            if (r != kUndecided) return r;
+            // some comparison was not decided by the intervals: decide the step exactly
+            score_staged<true>(n_new);
+            exactify_list();
+            ++n_exact;
         }
-        wave_sync();
+    }
 
-        // candidates in lanes [0, n_new); drop those not better than the ef-th key
-        const uint64_t key = (lane < n_new) ? st_key[lane] : kInf;
+    static constexpr int kUndecided = INT_MIN;
+
+    // Merges the scored candidates in st_key[0, n_new) into C.  Returns the smallest
+    // position at which an entry was inserted (INT_MAX if none), or kUndecided, with C
+    // unchanged, when an inexact key takes part in a comparison that its error could
+    // flip (never when all_exact: exact keys are equal only for equal ids).
+    __device__ int place(int n_new, bool all_exact) {
+        const bool lazy = !all_exact;
+        const uint64_t key = (lane < n_new) ? st_key[lane] : kInf;  // stored with its flags
+        const uint64_t kc = key & ~kFlags;                           // compared without
+        const uint32_t ko = hi32(key);
+        uint64_t cw[CH];
+#pragma unroll
+        for (int w = 0; w < CH; ++w) cw[w] = c[w] & ~kFlags;
+        if (lazy && __ballot(lane < n_new && (ko < kOrdLo || ko > kOrdHi)) != 0) return kUndecided;
+
+        // candidates in lanes [0, n_new); drop those not better than the ef-th key (equal
+        // keys: the same node)
         uint64_t cand = __ballot(lane < n_new);
         if (size == ef) {
-            const uint64_t kth = key_at(ef - 1) & ~1ull;
-            cand = __ballot(lane < n_new && key < kth);
+            const uint64_t kth = key_at(ef - 1) & ~kFlags;
+            cand = __ballot(lane < n_new && kc < kth);
+            if (lazy && __ballot(lane < n_new && kc != kth && near(ko, hi32(kth))) != 0) return kUndecided;
         }
         if (cand == 0) return INT_MAX;
 
-        // position of every candidate in C; candidates already in C are duplicates
+        // position of every candidate in C: a binary search over tmp, which mirrors C
+        // (checked flags aside); a candidate equal to an entry is a duplicate, and one
+        // close to a neighbouring entry is undecided (entries farther away are farther
+        // in the encoding too)
+        const bool is_cand = (cand >> lane) & 1ull;
         int pos = 0;
-        int minpos = INT_MAX;
-        uint64_t surv = cand;
-        for (uint64_t mm = cand; mm; mm &= mm - 1) {
-            const int j = __builtin_ctzll(mm);
-            const uint64_t kj = readlane64(key, j);
-            int p = 0;
-            bool dup = false;
-#pragma unroll
-            for (int w = 0; w < CH; ++w) {
-                const uint64_t cw = c[w] & ~1ull;
-                p += __popcll(__ballot(cw < kj));
-                dup = dup || (__ballot(cw == kj) != 0);
+        bool dup = false, open = false;
+        if (is_cand && size > 0) {
+            int step = 1;
+            while (step * 2 <= size) step *= 2;
+            for (; step > 0; step >>= 1) {
+                const int probe = pos + step - 1;
+                if (probe < size && (tmp[probe] & ~kFlags) < kc) pos += step;
             }
-            if (dup) {
-                surv &= ~(1ull << j);
-            } else {
-                if (lane == j) pos = p;
-                minpos = min(minpos, p);
+            if (pos < size) {
+                const uint64_t nx = tmp[pos] & ~kFlags;
+                dup = nx == kc;
+                open = !dup && near(hi32(nx), ko);
             }
+            if (pos > 0) open = open || near(hi32(tmp[pos - 1]), ko);
         }
+        uint64_t surv = cand & ~__ballot(dup);
+        if (lazy && __ballot(is_cand && !dup && open) != 0) return kUndecided;
         if (surv == 0) return INT_MAX;
+
+        // rank of every survivor among the survivors; shift of every entry of C.  The same
+        // id can arrive twice in one batch (when the cache could not store it); the later
+        // copy is dropped.
+        int rank = 0;
+        int shift[CH];
+        int minpos = INT_MAX;
+        while (true) {
+            const bool mine = (surv >> lane) & 1ull;
+            rank = 0;
+            minpos = INT_MAX;
+#pragma unroll
+            for (int w = 0; w < CH; ++w) shift[w] = 0;
+            uint64_t close = 0;
+            for (uint64_t mm = surv; mm; mm &= mm - 1) {
+                const int k = __builtin_ctzll(mm);
+                const uint64_t kk = readlane64(kc, k);
+                minpos = min(minpos, __builtin_amdgcn_readlane(pos, k));
+                rank += (kk < kc) ? 1 : 0;
+#pragma unroll
+                for (int w = 0; w < CH; ++w) shift[w] += (kk < cw[w]) ? 1 : 0;
+                close |= __ballot(mine && k != lane && near(hi32(kk), ko));
+            }
+            if (close == 0) break;
+            // rare: survivors close to each other; equal keys are the same node twice
+            bool drop = false, opn = false;
+            for (uint64_t mm = surv; mm; mm &= mm - 1) {
+                const int k = __builtin_ctzll(mm);
+                const uint64_t kk = readlane64(kc, k);
+                if (mine && k != lane && near(hi32(kk), ko)) {
+                    if (kk == kc) drop = drop || k < lane;
+                    else opn = true;
+                }
+            }
+            if (lazy && __ballot(opn) != 0) return kUndecided;
+            const uint64_t dropped = __ballot(drop);
+            if (dropped == 0) break;
+            surv &= ~dropped;
+        }
         const int n_ins = __popcll(surv);
         const bool mine = (surv >> lane) & 1ull;
 
-        // rank of every survivor among the survivors; shift of every entry of C
-        int rank = 0;
-        int shift[CH];
-#pragma unroll
-        for (int w = 0; w < CH; ++w) shift[w] = 0;
-        for (uint64_t mm = surv; mm; mm &= mm - 1) {
-            const int j = __builtin_ctzll(mm);
-            const uint64_t kj = readlane64(key, j);
-            rank += (kj < key) ? 1 : 0;
-#pragma unroll
-            for (int w = 0; w < CH; ++w) shift[w] += (kj < (c[w] & ~1ull)) ? 1 : 0;
-        }
-
         // merge: scatter old entries and survivors to their final positions, read back
+        wave_sync();  // the searches above have read tmp
 #pragma unroll
         for (int w = 0; w < CH; ++w) {
             const int t = w * 64 + lane;
@@ -371,10 +536,10 @@ struct Wave {
     }
 };
 
-// Small lists (CH <= 2) fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about
-// as many); larger lists keep the compiler's choice rather than spill.
+// Small lists (CH <= 2) fit without spills in 72 VGPRs with 16-bit rows (7 waves per
+// SIMD) and in 80 with fp32 rows (6 waves); larger lists keep the compiler's choice.
 template <int DT, int MET, int CH>
-__global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a) {
+__global__ __launch_bounds__(256, (CH <= 2 ? (DT == PA_F32 ? 6 : 7) : 1)) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
@@ -416,7 +581,7 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         for (int wi = 0; wi < CH; ++wi) {
             if (fu2 < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
                 const int t = wi * 64 + lane;
-                uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & 1ull));
+                uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & kChecked));
                 if (fu < 0 && mk) {
                     fu = wi * 64 + __builtin_ctzll(mk);
                     mk &= mk - 1;
@@ -436,12 +601,12 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         for (int wi = 0; wi < CH; ++wi) {
             if (wi == (fu >> 6)) {
                 ku = readlane64(w.c[wi], fu & 63);
-                if (lane == (fu & 63)) w.c[wi] |= 1ull;
+                if (lane == (fu & 63)) w.c[wi] |= kChecked;
             }
             if (fu2 >= 0 && wi == (fu2 >> 6)) ku2 = readlane64(w.c[wi], fu2 & 63);
         }
         lb = fu + 1;
-        const int u = uniform(static_cast<int>(static_cast<uint32_t>(ku) >> 1));
+        const int u = uniform(static_cast<int>(key_id(ku)));
         ++n_exp;
         int v = spec_v;
         if (u != spec_u) {
@@ -452,12 +617,13 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         spec_u = -1;
         spec_v = -1;
         if (fu2 >= 0) {
-            spec_u = uniform(static_cast<int>(static_cast<uint32_t>(ku2) >> 1));
+            spec_u = uniform(static_cast<int>(key_id(ku2)));
             if (lane < a.R) spec_v = a.adj[static_cast<int64_t>(spec_u) * a.R + lane];
         }
         const int mp = w.offer(v);
         lb = min(lb, mp);
     }
+    if (MET == PA_METRIC_L2) w.exactify_list();  // the output holds exact distances
     int32_t* oi = a.out_ids + qi * a.ef;
     float* od = a.out_d + qi * a.ef;
 #pragma unroll
@@ -465,7 +631,7 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         const int t = wi * 64 + lane;
         if (t < a.ef) {
             if (t < w.size) {
-                oi[t] = static_cast<int32_t>(static_cast<uint32_t>(w.c[wi]) >> 1);
+                oi[t] = static_cast<int32_t>(key_id(w.c[wi]));
                 od[t] = unord_f32(static_cast<uint32_t>(w.c[wi] >> 32));
             } else {
                 oi[t] = -1;
@@ -543,6 +709,7 @@ void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dty
     a.out_d = dists;
     a.counters = counters;
     require((1 << a.hlog) >= 4 * ((ef + 63) / 64 * 64), "visited cache must hold at least 4*ef entries");
+    require(N <= (int64_t{1} << 30), "the traversal supports at most 2^30 nodes (ids take 30 bits of a key)");
     require(a.row_bytes % 16 == 0, "reduced row must be a multiple of 16 bytes");
     require(a.cpr >= 1 && a.cpr <= 64, "reduced row must be 16..1024 bytes");
     if (xr_dtype == PA_F32) {
