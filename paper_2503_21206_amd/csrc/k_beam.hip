@@ -202,7 +202,9 @@ constexpr int wave_lds_bytes(int hlog) {
     return CH * 64 * 8 + 64 * 8 + 64 * 4 + (4 << hlog);
 }
 
-template <int DT, int MET, int CH>
+// GSL: log2 of the lanes per vector when fixed at compile time (the group reductions and
+// load offsets then fold to constants), or -1 to take it from the arguments.
+template <int DT, int MET, int CH, int GSL>
 struct Wave {
     static constexpr int EPC = Chunk<DT>::kElems;
     static constexpr int KC = kLaneElems / EPC;  // 16-byte chunks per lane per vector
@@ -225,10 +227,11 @@ struct Wave {
 
     __device__ Wave(const BeamArgs& args, unsigned char* base, int64_t qi, int lane_, int ef_) : a(args), lane(lane_) {
         ef = ef_;
-        gs = 1 << a.gs_log;
-        vpl = 64 >> a.gs_log;
+        const int gsl = GSL >= 0 ? GSL : a.gs_log;
+        gs = 1 << gsl;
+        vpl = 64 >> gsl;
         sub = lane & (gs - 1);
-        grp = lane >> a.gs_log;
+        grp = lane >> gsl;
         hmask = (1 << a.hlog) - 1;
         ragged = gs * KC > a.cpr;
         tmp = reinterpret_cast<uint64_t*>(base);
@@ -328,22 +331,20 @@ struct Wave {
     // or plain (then flagged inexact).  Every lane of the group returns the same key.
     template <bool EXACT>
     __device__ uint64_t score_row(uint32_t id, bool live) const {
-        const unsigned char* row = a.xr + static_cast<int64_t>(live ? id : 0u) * a.row_bytes;
+        // idle groups load row 0 (their keys are discarded)
+        const unsigned char* row = a.xr + static_cast<int64_t>(live ? id : 0u) * a.row_bytes + sub * 16;
         uint4 raw[KC];
-        if (live) {
+        if (!ragged) {
+#pragma unroll
+            for (int j = 0; j < KC; ++j) raw[j] = *reinterpret_cast<const uint4*>(row + j * gs * 16);
+        } else {  // chunks past the row are read from its last chunk, then zeroed
+            const uint4 zero = make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int j = 0; j < KC; ++j) {
-                const int ch = min(sub + j * gs, a.cpr - 1);
-                raw[j] = *reinterpret_cast<const uint4*>(row + static_cast<int64_t>(ch) * 16);
+                const int ch = sub + j * gs;
+                const uint4 v = *reinterpret_cast<const uint4*>(row + (min(ch, a.cpr - 1) - sub) * 16);
+                raw[j] = ch < a.cpr ? v : zero;
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < KC; ++j) raw[j] = make_uint4(0, 0, 0, 0);
-        }
-        if (ragged) {  // chunks past the row (loaded from its last chunk) are zero
-#pragma unroll
-            for (int j = 0; j < KC; ++j)
-                if (sub + j * gs >= a.cpr) raw[j] = make_uint4(0, 0, 0, 0);
         }
         if (EXACT) {
             const float s = group_sum(lane_partial(raw), gs);
@@ -536,9 +537,10 @@ struct Wave {
     }
 };
 
-// Small lists (CH <= 2) fit without spills in 72 VGPRs with 16-bit rows (7 waves per
-// SIMD) and in 80 with fp32 rows (6 waves); larger lists keep the compiler's choice.
-template <int DT, int MET, int CH>
+// Small lists (CH <= 2) fit in 72 VGPRs with 16-bit rows (7 waves per SIMD) and in 80
+// with fp32 rows (6 waves; a few values spill, outside the loops); larger lists keep the
+// compiler's choice.
+template <int DT, int MET, int CH, int GSL>
 __global__ __launch_bounds__(256, (CH <= 2 ? (DT == PA_F32 ? 6 : 7) : 1)) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(256, (CH <= 2 ? (DT == PA_F32 ? 6 : 7) : 1)) void b
     }
     ef = uniform(ef);
     E = uniform(E);
-    Wave<DT, MET, CH> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane, ef);
+    Wave<DT, MET, CH, GSL> w(a, smem + static_cast<size_t>(wid) * a.wave_bytes, qi, lane, ef);
     w.clear_cache();
 
     int n_exp = 0, n_reset = 0, aborted = 0;
@@ -648,22 +650,31 @@ __global__ __launch_bounds__(256, (CH <= 2 ? (DT == PA_F32 ? 6 : 7) : 1)) void b
     }
 }
 
-template <int DT, int MET, int CH>
+template <int DT, int MET, int CH, int GSL>
 void launch_typed(BeamArgs a, hipStream_t s) {
     a.wave_bytes = wave_lds_bytes<CH>(a.hlog);
     const int wpb = a.wave_bytes * 2 <= 64 * 1024 ? 2 : 1;
     const int blocks = static_cast<int>((a.m + wpb - 1) / wpb);
     const size_t lds = static_cast<size_t>(a.wave_bytes) * wpb;
-    hipLaunchKernelGGL((beam_kernel<DT, MET, CH>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((beam_kernel<DT, MET, CH, GSL>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+}
+
+// 4 and 8 lanes per vector (reduced rows of 64 to 128 fp32 or 128 to 256 16-bit elements)
+// get their own code; other widths take the lane count at run time.
+template <int DT, int MET, int CH>
+void launch_gs(const BeamArgs& a, hipStream_t s) {
+    if (a.gs_log == 2) launch_typed<DT, MET, CH, 2>(a, s);
+    else if (a.gs_log == 3) launch_typed<DT, MET, CH, 3>(a, s);
+    else launch_typed<DT, MET, CH, -1>(a, s);
 }
 
 template <int DT, int MET>
 void launch_ch(const BeamArgs& a, hipStream_t s) {
     const int ch = (a.ef + 63) / 64;
-    if (ch <= 1) launch_typed<DT, MET, 1>(a, s);
-    else if (ch <= 2) launch_typed<DT, MET, 2>(a, s);
-    else if (ch <= 4) launch_typed<DT, MET, 4>(a, s);
-    else launch_typed<DT, MET, 8>(a, s);
+    if (ch <= 1) launch_gs<DT, MET, 1>(a, s);
+    else if (ch <= 2) launch_gs<DT, MET, 2>(a, s);
+    else if (ch <= 4) launch_gs<DT, MET, 4>(a, s);
+    else launch_gs<DT, MET, 8>(a, s);
 }
 
 }  // namespace
