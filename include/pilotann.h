@@ -61,6 +61,9 @@ typedef int32_t pa_status;
 #define PA_SAMPLE_UNIFORM 0
 #define PA_SAMPLE_SEED_EXPAND 1
 
+#define PA_VISITED_EXACT 0 /* stage-1 visited set: exact (bounded LDS cache that only forgets) */
+#define PA_VISITED_BLOOM 1 /* stage-1 visited set: the paper's lossy Bloom filter in LDS       */
+
 #define PA_MAX_EF 512    /* largest candidate-list size of the GPU traversal */
 #define PA_MAX_DEGREE 64 /* largest subgraph out-degree                       */
 #define PA_MAX_DR 256    /* largest reduced dimension                         */
@@ -209,6 +212,22 @@ pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const voi
                           const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
                           int32_t cache_log2, int32_t* ids_dev, float* d_dev,
                           int32_t* counters_dev, void* stream);
+
+/* Stage 1 with the paper's visited filter (section 4.3): as pa_gpu_traverse, except that
+ * each query tracks visited nodes in a Bloom filter of 2^filter_log2 bits in LDS
+ * (13..18; 0 = automatic, the same bytes as the automatic exact cache) with two hashes,
+ * bit_i(v) = ((uint32)v * A_i mod 2^32) >> (32 - filter_log2), A_1 = 0x9E3779B1,
+ * A_2 = 0x85EBCA77.  A node whose two bits are set counts as visited, also when other
+ * nodes set them (a false positive: it is never scored here).  The ids of one adjacency
+ * row (and each group of 64 entries) are all tested against the filter as it was before
+ * the group, then their bits are set; an id that appears twice in a group is scored twice
+ * and listed once.  The result is Algorithm 1 with this visited rule; counters as for
+ * pa_gpu_traverse with counters[i][2] = 0. */
+pa_status pa_gpu_traverse_bloom(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
+                                int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
+                                const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
+                                int32_t filter_log2, int32_t* ids_dev, float* d_dev,
+                                int32_t* counters_dev, void* stream);
 
 /* Stage 1 with a list size per query, so that requests of uneven ef share one launch
  * (used by the serving loop).  As pa_gpu_traverse, plus ef_dev [m] int32 with
@@ -364,6 +383,9 @@ typedef struct {
                              resident in HBM and complete (its writes finished);
                              the GPU stage then reads the queries from it and skips
                              their upload.  Q_host is still read by stages 2-3.  */
+    int32_t visited;      /* stage-1 visited set: PA_VISITED_EXACT (0) or
+                             PA_VISITED_BLOOM (cache_log2 then sizes the filter:
+                             32 << cache_log2 bits)                                 */
 } pa_search_opts;
 
 typedef struct {

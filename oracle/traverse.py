@@ -11,7 +11,8 @@ Readings where the paper is silent:
   initialised (entries already visited, or equal to -1, are skipped), and the
   initial C is resized to ef (the first expansion is the same either way);
 * visited is an exact set, one distance per visited node, so
-  n_dist = |visited| (the paper's lossy GPU filter is a separate variant);
+  n_dist = |visited|; ``bloom_log2`` selects the paper's lossy filter instead
+  (section 4.3; its readings are in ``oracle.bloom``);
 * expansion width is one node per loop step, as printed;
 * distances are single-precision values (section 6.1): each is computed exactly
   and rounded once to fp32 before it enters C (``precision="f64"`` keeps fp64).
@@ -32,6 +33,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .bloom import ENTRY_GROUP, BloomFilter
 from .metric import as_f32, delta_many
 
 
@@ -47,7 +49,7 @@ def _resize_gap(sorted_keys, ef: int) -> float:
 
 
 def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "l2", *,
-                  initial=None, visited=None, max_steps=None, precision: str = "f32"):
+                  initial=None, visited=None, max_steps=None, precision: str = "f32", bloom_log2=None):
     """Run Algorithm 1 for one query.
 
     q        query vector (any float dtype; used in fp64)
@@ -55,12 +57,15 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
     rowptr, nbrs   CSR out-neighbours in stored order
     Returns a dict with ``ids``/``dists`` (C in key order, at most ef),
     ``checked`` flags, ``n_exp`` (loop steps), ``n_dist`` (distances computed
-    here), ``visited`` (the final set) and ``margin``.
+    here), ``visited`` (the final set, or the Bloom filter) and ``margin``.
     """
     if ef < 1:
         raise ValueError("ef must be >= 1")
+    if bloom_log2 is not None and (initial is not None or visited is not None):
+        raise ValueError("the Bloom filter variant starts from entry points only")
     q = np.asarray(q, dtype=np.float64)
     seen = set() if visited is None else set(int(v) for v in visited)
+    bloom = BloomFilter(bloom_log2) if bloom_log2 is not None else None
     n_dist = 0
 
     def score(ids):
@@ -73,17 +78,25 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
             C.append([(float(d), int(v)), False])
             seen.add(int(v))
     fresh = []
-    for e in entries:
-        e = int(e)
-        if e < 0 or e in seen:
-            continue
-        seen.add(e)
-        fresh.append(e)
+    if bloom is not None:
+        entries = [int(e) for e in entries]
+        for g in range(0, len(entries), ENTRY_GROUP):
+            fresh += bloom.fresh_of_group(entries[g:g + ENTRY_GROUP])
+    else:
+        for e in entries:
+            e = int(e)
+            if e < 0 or e in seen:
+                continue
+            seen.add(e)
+            fresh.append(e)
     if fresh:
         ds = score(fresh)
         n_dist += len(fresh)
+        in_c = set()
         for d, v in zip(ds, fresh):
-            C.append([(float(d), v), False])
+            if v not in in_c:  # an id listed twice in a group enters C once
+                in_c.add(v)
+                C.append([(float(d), v), False])
     C.sort(key=lambda c: c[0])
     margin = _resize_gap([c[0] for c in C], ef)
     del C[ef:]
@@ -101,16 +114,22 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
         n_exp += 1
         # lines 6-10: unvisited out-neighbours, mark, score, insert
         new = []
-        for v in nbrs[rowptr[u]:rowptr[u + 1]]:
-            v = int(v)
-            if v not in seen:
-                seen.add(v)
-                new.append(v)
+        if bloom is not None:
+            new = bloom.fresh_of_group(nbrs[rowptr[u]:rowptr[u + 1]])
+        else:
+            for v in nbrs[rowptr[u]:rowptr[u + 1]]:
+                v = int(v)
+                if v not in seen:
+                    seen.add(v)
+                    new.append(v)
         if new:
             ds = score(new)
             n_dist += len(new)
+            in_c = {c[0][1] for c in C}
             for d, v in zip(ds, new):
-                C.append([(float(d), v), False])
+                if v not in in_c:
+                    in_c.add(v)
+                    C.append([(float(d), v), False])
             C.sort(key=lambda c: c[0])
             margin = min(margin, _resize_gap([c[0] for c in C], ef))
         # line 11: C.resize(ef)
@@ -123,6 +142,6 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
         "checked": np.asarray([c[1] for c in C], dtype=bool),
         "n_exp": n_exp,
         "n_dist": n_dist,
-        "visited": seen,
+        "visited": bloom if bloom is not None else seen,
         "margin": margin,
     }

@@ -22,6 +22,7 @@ PA_OK = 0
 PA_METRIC_L2, PA_METRIC_IP = 0, 1
 PA_F32, PA_F16, PA_BF16, PA_FP8E4M3 = 0, 1, 2, 3
 PA_SAMPLE_UNIFORM, PA_SAMPLE_SEED_EXPAND = 0, 1
+PA_VISITED_EXACT, PA_VISITED_BLOOM = 0, 1
 PA_MAX_EF = 512
 
 METRICS = {"l2": PA_METRIC_L2, "ip": PA_METRIC_IP}
@@ -44,7 +45,7 @@ class Params(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("ef_gpu", C.c_int32), ("ef_cpu", C.c_int32), ("E", C.c_int32), ("batch", C.c_int32),
                 ("stage_mask", C.c_int32), ("cache_log2", C.c_int32), ("threads", C.c_int32),
-                ("handoff", C.c_int32), ("q_dev", C.c_void_p)]
+                ("handoff", C.c_int32), ("q_dev", C.c_void_p), ("visited", C.c_int32)]
 
 
 class SearchStats(C.Structure):
@@ -90,6 +91,8 @@ _SIGS = {
     "pa_build_entries": [_P, _I32, _I32, _I32, _P, _I32, _P, _P],
     "pa_select_entries": [_P, _P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P],
     "pa_gpu_traverse": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P],
+    "pa_gpu_traverse_bloom": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
+                              _P],
     "pa_cpu_stages": [_P, _I64, _I32, _P, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _I32,
                       _P, _P, _P],
     "pa_cpu_search": [_P, _I64, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P],
@@ -334,8 +337,10 @@ def select_entries_fp8(Qr, cluster, EV, EV8, EVscale, EVnorm, EVid, E: int, K: i
     return ids, dist
 
 
-def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: int = 0, stream=None):
-    """Stage 1 on device tensors -> (ids [m][ef] int32, dists [m][ef] fp32, counters [m][4] int32)."""
+def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: int = 0, stream=None,
+                 bloom_log2: int = -1):
+    """Stage 1 on device tensors -> (ids [m][ef] int32, dists [m][ef] fp32, counters [m][4] int32).
+    bloom_log2 >= 0 selects the Bloom-filter visited set of 2^bloom_log2 bits (0: automatic)."""
     import torch
     m, d_r = Qr.shape
     N, R = adj.shape
@@ -348,9 +353,11 @@ def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: 
     ids = torch.empty((m, ef), dtype=torch.int32, device=Qr.device)
     dist = torch.empty((m, ef), dtype=torch.float32, device=Qr.device)
     cnt = torch.empty((m, 4), dtype=torch.int32, device=Qr.device)
-    _check(lib().pa_gpu_traverse(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
-                                 _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E, ef,
-                                 METRICS[metric], cache_log2, _dev(ids), _dev(dist), _dev(cnt), _stream(stream)))
+    fn = lib().pa_gpu_traverse if bloom_log2 < 0 else lib().pa_gpu_traverse_bloom
+    _check(fn(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
+              _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E, ef,
+              METRICS[metric], cache_log2 if bloom_log2 < 0 else bloom_log2, _dev(ids), _dev(dist), _dev(cnt),
+              _stream(stream)))
     return ids, dist, cnt
 
 
@@ -521,9 +528,11 @@ class Index:
 
     def search(self, Q, k: int, ef_gpu: int, ef_cpu: int = 0, E: int = 0, batch: int = 0, stage_mask: int = 0,
                cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0,
-               Q_dev=None):
+               Q_dev=None, bloom: bool = False):
         """Q_dev: optional torch tensor on the index's device holding the same [m][dim] fp32
-        queries as Q; the GPU stage then reads them from HBM instead of uploading Q."""
+        queries as Q; the GPU stage then reads them from HBM instead of uploading Q.
+        bloom: stage 1 tracks visited nodes in the paper's Bloom filter (32 << cache_log2
+        bits) instead of the exact set."""
         Q, pq = _host(Q, np.float32)
         m = Q.shape[0]
         if Q.ndim != 2 or Q.shape[1] != self.cfg.dim:
@@ -539,7 +548,7 @@ class Index:
         ids = np.empty((m, k), dtype=np.int64)
         dist = np.empty((m, k), dtype=np.float32)
         cnt = np.empty((m, 8), dtype=np.int32) if with_counters else None
-        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd)
+        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd, 1 if bloom else 0)
         st = SearchStats()
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))

@@ -18,6 +18,13 @@
 // evolves exactly as in Algorithm 1; only the count of distance evaluations can exceed
 // |visited| (reported per query together with the number of forget events).
 //
+// The paper's own visited set is available as an option: a Bloom filter of 32 << hlog
+// bits in the same LDS words, two multiplicative hashes per id.  A node whose two bits
+// are set counts as visited, also when other nodes set them (a false positive: the node
+// is never scored, as in the paper; the host stages can still reach it).  All ids of a
+// batch are tested against the filter as it was before the batch, then their bits are
+// set, so the outcome does not depend on the order of the lanes' atomics.
+//
 // Distances (L2).  Every decision must follow the exact distance rounded once to fp32.
 // A plain fp32 sum of 16 fused squares per lane plus the lane reduction lies within a
 // few dozen units of the orderable encoding of the correctly rounded exact distance, so
@@ -54,6 +61,8 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint64_t kInf = ~0ull;
 constexpr int kLaneElems = 16;  // vector elements each lane scores per gathered vector
 constexpr int kProbes = 16;
+constexpr uint32_t kBloomA = 0x9E3779B1u;  // multipliers of the Bloom filter's two hashes
+constexpr uint32_t kBloomB = 0x85EBCA77u;
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
     uint32_t u = __float_as_uint(f);
@@ -153,6 +162,7 @@ struct BeamArgs {
     int gs_log;  // log2 of lanes per gathered vector (each lane holds kLaneElems elements)
     int cpr;     // 16-byte chunks per reduced row
     int wave_bytes;
+    int bloom;  // 1: the visited set is the Bloom filter described above
     int32_t* out_ids;
     float* out_d;
     int32_t* counters;
@@ -258,9 +268,24 @@ struct Wave {
     }
 
     __device__ void clear_cache() {
-        for (int i = lane; i <= hmask; i += 64) cache[i] = kEmpty;
+        const uint32_t empty = a.bloom ? 0u : kEmpty;
+        for (int i = lane; i <= hmask; i += 64) cache[i] = empty;
         fill = 0;
         wave_sync();
+    }
+
+    // Bloom filter: bit (v * A mod 2^32) >> (32 - log2 bits) for the two multipliers.
+    __device__ uint32_t bloom_bit(int v, uint32_t mul) const {
+        return (static_cast<uint32_t>(v) * mul) >> (32 - (a.hlog + 5));
+    }
+    __device__ bool bloom_seen(int v) const {
+        const uint32_t b1 = bloom_bit(v, kBloomA), b2 = bloom_bit(v, kBloomB);
+        return ((cache[b1 >> 5] >> (b1 & 31)) & (cache[b2 >> 5] >> (b2 & 31)) & 1u) != 0;
+    }
+    __device__ void bloom_add(int v) {
+        const uint32_t b1 = bloom_bit(v, kBloomA), b2 = bloom_bit(v, kBloomB);
+        atomicOr(&cache[b1 >> 5], 1u << (b1 & 31));
+        atomicOr(&cache[b2 >> 5], 1u << (b2 & 31));
     }
 
     // Test-and-set of v in the visited cache; true when v must be scored.
@@ -397,10 +422,17 @@ struct Wave {
     // Offer one id per lane (-1 = none) to C.  Returns the smallest position at which an
     // entry was inserted (INT_MAX if none).
     __device__ int offer(int v) {
-        bool stored;
-        const bool fresh = test_and_set(v, stored);
-        fill += __popcll(__ballot(stored));
-        forgot += __popcll(__ballot(fresh && !stored));  // scored but not remembered
+        bool fresh;
+        if (a.bloom) {
+            fresh = v >= 0 && !bloom_seen(v);
+            wave_sync();  // every test of the batch has read the filter before any bit is set
+            if (fresh) bloom_add(v);
+        } else {
+            bool stored;
+            fresh = test_and_set(v, stored);
+            fill += __popcll(__ballot(stored));
+            forgot += __popcll(__ballot(fresh && !stored));  // scored but not remembered
+        }
         const uint64_t newmask = __ballot(fresh);
         const int n_new = __popcll(newmask);
         if (n_new == 0) return INT_MAX;
@@ -694,10 +726,11 @@ int beam_auto_cache_log2(int ef, int R) {
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
-                 const int32_t* efq) {
+                 const int32_t* efq, int visited) {
     if (m == 0) return;
     BeamArgs a{};
     a.efq = efq;
+    a.bloom = visited == PA_VISITED_BLOOM ? 1 : 0;
     a.qr = Qr;
     a.m = m;
     a.d_r = d_r;

@@ -176,6 +176,26 @@ def test_traverse_edge_cases(dev, tiny):
         pa.gpu_traverse(Qr, Xr, adj, _t(ent[:4].astype(np.int32), dev), 513)
 
 
+def test_traverse_bloom_filter_parity(dev, tiny):
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    Xr = _t(tiny["Xr32"], dev)
+    for lg, ef, nq in ((13, 64, 300), (15, 64, 300), (18, 32, 300), (16, 200, 60)):
+        say(f"gpu_traverse with the Bloom visited filter: 2^{lg} bits, ef={ef}, {nq} queries")
+        _, _, cnt = _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, ef, np.arange(nq), bloom_log2=lg)
+        assert (cnt[:, 2] == 0).all()
+    say("Bloom filter with fp16 rows and duplicate / out-of-range entries")
+    xh = to_f16(tiny["Xr32"])
+    bad = ent.copy()
+    bad[:, 1] = bad[:, 0]
+    bad[:, 2] = 10 ** 6
+    _traverse_check(dev, tiny, np.asarray(xh, dtype=np.float32), _t(np.asarray(xh, dtype=np.float32), dev,
+                    torch.float16), bad, 48, np.arange(200), bloom_log2=14)
+    Qr = _t(tiny["Qr32"][:4], dev)
+    adj = _t(tiny["sub_adj"].astype(np.int32), dev)
+    with pytest.raises(pa.PilotannError):  # a filter below 128 bits per list entry
+        pa.gpu_traverse(Qr, Xr, adj, _t(ent[:4].astype(np.int32), dev), 256, bloom_log2=13)
+
+
 def test_traverse_f16_and_bf16(dev, tiny):
     ent, _, _, _ = oracle_entries(tiny, 8)
     for name, conv, tdt in (("f16", to_f16, torch.float16), ("bf16", to_bf16, torch.bfloat16)):
@@ -258,12 +278,26 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     ids_d, d_d, _, _ = idx.search(Q, 10, 64, 64, batch=300, Q_dev=Qd)
     assert (ids_d == ids).all() and (d_d.view(np.uint32) == d.view(np.uint32)).all()
     import ctypes
-    opts = pa.SearchOpts(64, 64, 0, 0, 0, 0, 0, 0, Q.ctypes.data)  # a host pointer is refused
+    opts = pa.SearchOpts(64, 64, 0, 0, 0, 0, 0, 0, Q.ctypes.data, 0)  # a host pointer is refused
     out_i = np.empty((Q.shape[0], 10), np.int64)
     out_d = np.empty((Q.shape[0], 10), np.float32)
     st = pa.lib().pa_search(idx._h, Q.ctypes.data_as(ctypes.c_void_p), Q.shape[0], 10, ctypes.byref(opts),
                             out_i.ctypes.data_as(ctypes.c_void_p), out_d.ctypes.data_as(ctypes.c_void_p), None, None)
     assert st == -1
+    # stage 1 with the paper's Bloom visited filter (automatic size: 2^15 bits at ef 64)
+    ids_b, d_b, cnt_b, _ = idx.search(Q, 10, 64, 64, with_counters=True, batch=300, bloom=True)
+    assert (cnt_b[:, 2] == 0).all()
+    bi, _, _ = oracle.pipeline(Q[:200], tiny["X"], tiny["V32"], tiny["rp"], tiny["nb"], tiny["sr"], tiny["sn"],
+                               tiny["Xr32"], tiny["cent32"], tiny["buckets"], P64, tiny["pivots"], k=10,
+                               ef_gpu=64, ef_cpu=64, E=8, bloom_log2=15)
+    same_b = np.mean([(ids_b[i] == bi[i]).all() for i in range(200)])
+    rec_b = oracle.recall_at_k(ids_b, gt, 10)
+    say(f"Bloom filter: recall@10 {rec_b:.4f}, {same_b:.3f} of 200 lists equal to the oracle's")
+    assert same_b >= 0.97 and rec_b >= rec - 0.02
+    tally = DistTally()
+    for i in range(200):
+        tally.check(d_b[i], oracle.as_f32(oracle.delta_many(Q[i], tiny["X"][ids_b[i]])), i)
+    tally.done()
     # graceful degradation: no GPU stage = plain greedy search from the FES entries
     ids0, _, cnt0, _ = idx.search(Q[:100], 10, 64, 64, stage_mask=2, with_counters=True)
     assert (cnt0[:, 0] == 0).all()
