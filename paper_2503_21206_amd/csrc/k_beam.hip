@@ -362,13 +362,11 @@ struct Wave {
         if (!ragged) {
 #pragma unroll
             for (int j = 0; j < KC; ++j) raw[j] = *reinterpret_cast<const uint4*>(row + j * gs * 16);
-        } else {  // chunks past the row are read from its last chunk, then zeroed
-            const uint4 zero = make_uint4(0, 0, 0, 0);
+        } else {  // chunks past the row stay zero
 #pragma unroll
             for (int j = 0; j < KC; ++j) {
-                const int ch = sub + j * gs;
-                const uint4 v = *reinterpret_cast<const uint4*>(row + (min(ch, a.cpr - 1) - sub) * 16);
-                raw[j] = ch < a.cpr ? v : zero;
+                raw[j] = make_uint4(0, 0, 0, 0);
+                if (sub + j * gs < a.cpr) raw[j] = *reinterpret_cast<const uint4*>(row + j * gs * 16);
             }
         }
         if (EXACT) {
@@ -569,11 +567,11 @@ struct Wave {
     }
 };
 
-// Small lists (CH <= 2) fit in 72 VGPRs with 16-bit rows (7 waves per SIMD) and in 80
-// with fp32 rows (6 waves; a few values spill, outside the loops); larger lists keep the
-// compiler's choice.
+// Small lists (CH <= 2) fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about
+// as many; only the fp32 variant with two registers and a run-time lane count spills a
+// few values); larger lists keep the compiler's choice.
 template <int DT, int MET, int CH, int GSL>
-__global__ __launch_bounds__(256, (CH <= 2 ? (DT == PA_F32 ? 6 : 7) : 1)) void beam_kernel(BeamArgs a) {
+__global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
