@@ -287,6 +287,10 @@ typedef struct {
     int32_t pivot_dtype;  /* PA_F32 or PA_FP8E4M3 (precision form of entry selection)   */
     int32_t preselect;    /* FP8 form: pivots re-scored in fp32 per query = preselect*E
                              (0: 4), capped by the bucket size                         */
+    int32_t compact;      /* 1: HBM holds X_r and the subgraph for the sampled nodes
+                             only (memory-bounded layout, section 4.3 drops the
+                             unsampled nodes' vectors; see pa_index_build_subgraph);
+                             0: X_r for all N rows                                     */
 } pa_params;
 
 /* Create an empty index.  params is copied.  *out receives the handle (library-owned;
@@ -301,8 +305,9 @@ pa_status pa_index_set_data(pa_index* idx, const float* X_host, int64_t N,
                             const int64_t* rowptr_host, const int32_t* nbrs_host);
 
 /* Fit the projection on the attached X (pa_fit_projection) and write the reduced base
- * vectors of all N rows to HBM in xr_dtype.  center: 1 centred, 0 uncentred, -1 the
- * metric's default (centred for L2, uncentred for IP). */
+ * vectors of all N rows to HBM in xr_dtype (compact layout: of the sampled rows, once
+ * the subgraph is built).  center: 1 centred, 0 uncentred, -1 the metric's default
+ * (centred for L2, uncentred for IP). */
 pa_status pa_index_fit_projection(pa_index* idx, int32_t center);
 
 /* Use a caller-supplied projection V_host [D][d_r] fp32 instead of fitting one. */
@@ -313,7 +318,12 @@ pa_status pa_index_sample_nodes(pa_index* idx, const int64_t* order_host, int64_
                                 int32_t mode, uint8_t* mask_host);
 
 /* build_subgraph: validate (pa_check_subgraph against mask_host) and upload the
- * reconnected subgraph; a host copy is kept for stage 2. */
+ * reconnected subgraph; a host copy is kept for stage 2.  Compact layout: the n_s
+ * sampled nodes get device ids 0..n_s-1 in increasing node-id order (so ties between
+ * equal distances break the same way), X_r and the adjacency are stored for them only
+ * (n_s rows instead of N, ids rewritten), and stage 1 maps its output back to node
+ * ids; results equal the full layout's (with the Bloom filter the hashes see the
+ * device ids, so its false positives differ).  The reduced rows are (re)written here. */
 pa_status pa_index_build_subgraph(pa_index* idx, const uint8_t* mask_host,
                                   const int64_t* rowptr_host, const int32_t* nbrs_host);
 
@@ -359,11 +369,15 @@ typedef struct {
     int32_t n_pivots;    /* entry pivots, r buckets of n_pivots / r (0 before)  */
     int32_t built;       /* bit 0 data, bit 1 projection, bit 2 subgraph, bit 3 entries */
     int64_t hbm_bytes;   /* device bytes the index holds, work buffers included */
+    int64_t xr_rows;     /* rows of X_r and of the device subgraph (N, or n_s when
+                            compact; 0 before they are written)                  */
 } pa_index_info;
 
 pa_status pa_index_get_info(const pa_index* idx, pa_index_info* out);
 
-/* Device pointers of the index's tables (for stage-isolated calls); any may be NULL. */
+/* Device pointers of the index's tables (for stage-isolated calls); any may be NULL.
+ * In the compact layout X_r, the adjacency and EVid hold device ids (see
+ * pa_index_build_subgraph). */
 pa_status pa_index_device_tables(const pa_index* idx, const void** Xr_dev,
                                  const int32_t** adj_dev, const float** V_dev,
                                  const float** centroids_dev, const float** EV_dev,

@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [("dim", C.c_int32), ("d_r", C.c_int32), ("metric", C.c_int32), ("xr_dtype", C.c_int32),
                 ("r", C.c_int32), ("refine_steps", C.c_int32), ("threads", C.c_int32),
                 ("device", C.c_int32), ("hbm_budget", C.c_int64), ("pivot_dtype", C.c_int32),
-                ("preselect", C.c_int32)]
+                ("preselect", C.c_int32), ("compact", C.c_int32)]
 
 
 class SearchOpts(C.Structure):
@@ -60,7 +60,7 @@ class SearchStats(C.Structure):
 
 class IndexInfo(C.Structure):
     _fields_ = [("N", C.c_int64), ("R_full", C.c_int32), ("R_sub", C.c_int32), ("n_pivots", C.c_int32),
-                ("built", C.c_int32), ("hbm_bytes", C.c_int64)]
+                ("built", C.c_int32), ("hbm_bytes", C.c_int64), ("xr_rows", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -433,6 +433,7 @@ class IndexConfig:
     hbm_budget: int = 0
     pivot_dtype: str = "f32"  # "f32" | "fp8"
     preselect: int = 0
+    compact: bool = False  # X_r and the device subgraph for the sampled nodes only
 
 
 class Index:
@@ -442,7 +443,7 @@ class Index:
         self.cfg = cfg
         p = Params(cfg.dim, cfg.d_r, METRICS[cfg.metric], DTYPES[cfg.xr_dtype], cfg.r, cfg.refine_steps,
                    cfg.threads, cfg.device, cfg.hbm_budget, {"f32": PA_F32, "fp8": PA_FP8E4M3}[cfg.pivot_dtype],
-                   cfg.preselect)
+                   cfg.preselect, 1 if cfg.compact else 0)
         h = C.c_void_p()
         _check(lib().pa_index_create(C.byref(p), C.byref(h)))
         self._h = h

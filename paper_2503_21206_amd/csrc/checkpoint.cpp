@@ -1,5 +1,6 @@
 // Checkpoint of a built index: header + checksummed sections (pa_index_save / pa_index_load),
 // and the index's sizes (pa_index_get_info).
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -13,9 +14,9 @@ namespace pa {
 namespace {
 
 constexpr char kMagic[8] = {'P', 'A', 'N', 'N', 'I', 'D', 'X', '\0'};
-constexpr uint32_t kFormat = 1;
+constexpr uint32_t kFormat = 2;
 
-enum Tag : uint32_t { kV = 1, kXr = 2, kSub = 3, kCent = 4, kBucketIds = 5, kEV = 6, kEVn = 7 };
+enum Tag : uint32_t { kV = 1, kXr = 2, kSub = 3, kCent = 4, kBucketIds = 5, kEV = 6, kEVn = 7, kCid = 8 };
 
 struct Header {
     char magic[8];
@@ -24,6 +25,8 @@ struct Header {
     int32_t R_sub, n_b;
     int64_t N;
     int64_t n_sections;
+    int32_t compact, pad;
+    int64_t xr_rows;  // rows of X_r as stored (N, or the sampled nodes when compact)
 };
 
 struct SectionHead {
@@ -132,6 +135,7 @@ pa_status pa_index_get_info(const pa_index* idx, pa_index_info* out) {
         out->built = (idx->has_data ? 1 : 0) | (idx->has_proj ? 2 : 0) | (idx->has_sub ? 4 : 0) |
                      (idx->has_entries ? 8 : 0);
         out->hbm_bytes = idx->hbm_used;
+        out->xr_rows = idx->xr_rows;
     });
 }
 
@@ -155,7 +159,9 @@ pa_status pa_index_save(const pa_index* idx, const char* path) {
         h.R_sub = idx->R_sub;
         h.n_b = idx->n_b;
         h.N = idx->N;
-        h.n_sections = 7;
+        h.compact = idx->p.compact;
+        h.xr_rows = idx->xr_rows;
+        h.n_sections = idx->p.compact ? 8 : 7;
         std::vector<float> EV(static_cast<size_t>(n_p) * idx->p.d_r), EVn(static_cast<size_t>(n_p));
         PA_HIP(hipMemcpy(EV.data(), idx->EV_dev.p, sizeof(float) * EV.size(), hipMemcpyDeviceToHost));
         PA_HIP(hipMemcpy(EVn.data(), idx->EVn_dev.p, sizeof(float) * EVn.size(), hipMemcpyDeviceToHost));
@@ -164,12 +170,13 @@ pa_status pa_index_save(const pa_index* idx, const char* path) {
         const uint64_t hf = fnv1a(&h, sizeof h);
         out.write(&hf, sizeof hf);
         write_section(out, kV, idx->V.data(), sizeof(float) * idx->V.size());
-        write_device_section(out, kXr, idx->Xr_dev.p, static_cast<size_t>(idx->N) * idx->p.d_r * es);
+        write_device_section(out, kXr, idx->Xr_dev.p, static_cast<size_t>(idx->xr_rows) * idx->p.d_r * es);
         write_section(out, kSub, idx->sub_adj.data(), sizeof(int32_t) * idx->sub_adj.size());
         write_section(out, kCent, idx->centroids.data(), sizeof(float) * idx->centroids.size());
         write_section(out, kBucketIds, idx->bucket_ids.data(), sizeof(int32_t) * idx->bucket_ids.size());
         write_section(out, kEV, EV.data(), sizeof(float) * EV.size());
         write_section(out, kEVn, EVn.data(), sizeof(float) * EVn.size());
+        if (idx->p.compact) write_section(out, kCid, idx->cid.data(), sizeof(int32_t) * idx->cid.size());
         out.close();
     });
 }
@@ -188,26 +195,41 @@ pa_status pa_index_load(pa_index* idx, const char* path) {
         if (h.format != kFormat) fail(PA_EIO, in.path + ": unknown format " + std::to_string(h.format));
         const pa_params& p = idx->p;
         require(h.dim == p.dim && h.d_r == p.d_r && h.metric == p.metric && h.xr_dtype == p.xr_dtype && h.r == p.r &&
-                    h.pivot_dtype == p.pivot_dtype,
-                "checkpoint parameters differ from the index's (dim, d_r, metric, xr_dtype, r, pivot_dtype)");
+                    h.pivot_dtype == p.pivot_dtype && h.compact == p.compact,
+                "checkpoint parameters differ from the index's (dim, d_r, metric, xr_dtype, r, pivot_dtype, compact)");
         require(h.N == idx->N, "checkpoint holds N=" + std::to_string(h.N) + ", the index's data has N=" +
                                    std::to_string(idx->N));
-        if (h.R_sub < 1 || h.R_sub > PA_MAX_DEGREE || h.n_b < 1 || h.n_sections != 7)
+        if (h.R_sub < 1 || h.R_sub > PA_MAX_DEGREE || h.n_b < 1 || h.n_sections != (h.compact ? 8 : 7) ||
+            h.xr_rows < 0 || h.xr_rows > h.N || (!h.compact && h.xr_rows != h.N))
             fail(PA_EIO, in.path + ": corrupt header");
         const size_t es = dtype_size(h.xr_dtype);
         const size_t n_p = static_cast<size_t>(h.r) * h.n_b;
         // read and verify everything before the index is touched
         auto V = as<float>(read_section(in, kV, sizeof(float) * p.dim * p.d_r));
-        auto Xr = read_section(in, kXr, static_cast<size_t>(h.N) * p.d_r * es);
+        auto Xr = read_section(in, kXr, static_cast<size_t>(h.xr_rows) * p.d_r * es);
         auto sub = as<int32_t>(read_section(in, kSub, sizeof(int32_t) * static_cast<size_t>(h.N) * h.R_sub));
         auto cent = as<float>(read_section(in, kCent, sizeof(float) * p.r * p.d_r));
         auto bids = as<int32_t>(read_section(in, kBucketIds, sizeof(int32_t) * n_p));
         auto EV = as<float>(read_section(in, kEV, sizeof(float) * n_p * p.d_r));
         auto EVn = as<float>(read_section(in, kEVn, sizeof(float) * n_p));
+        std::vector<int32_t> cid;
+        if (h.compact) {
+            cid = as<int32_t>(read_section(in, kCid, sizeof(int32_t) * static_cast<size_t>(h.xr_rows)));
+            for (size_t i = 0; i < cid.size(); ++i)
+                if (cid[i] < 0 || cid[i] >= h.N || (i > 0 && cid[i] <= cid[i - 1]))
+                    fail(PA_EIO, in.path + ": the sampled-node list is not increasing within [0, N)");
+        }
         for (int32_t v : sub)
             if (v < -1 || v >= h.N) fail(PA_EIO, in.path + ": subgraph id out of range");
         for (int32_t v : bids)
             if (v < 0 || v >= h.N) fail(PA_EIO, in.path + ": pivot id out of range");
+        std::vector<int32_t> dev_ids(bids);  // the pivots' device ids
+        if (h.compact)
+            for (auto& v : dev_ids) {
+                const auto it = std::lower_bound(cid.begin(), cid.end(), v);
+                if (it == cid.end() || *it != v) fail(PA_EIO, in.path + ": a pivot is not a sampled node");
+                v = static_cast<int32_t>(it - cid.begin());
+            }
 
         PA_HIP(hipSetDevice(p.device));
         idx->has_proj = idx->has_sub = idx->has_entries = false;
@@ -215,13 +237,17 @@ pa_status pa_index_load(pa_index* idx, const char* path) {
             b.ensure(bytes, idx->hbm_used, p.hbm_budget);
             PA_HIP(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
         };
+        idx->cid = std::move(cid);
+        idx->xr_rows = 0;
+        idx->sub_adj = std::move(sub);
+        idx->R_sub = h.R_sub;
         up(idx->V_dev, V.data(), sizeof(float) * V.size());
-        up(idx->Xr_dev, Xr.data(), Xr.size());
-        up(idx->adj_dev, sub.data(), sizeof(int32_t) * sub.size());
+        if (!Xr.empty()) up(idx->Xr_dev, Xr.data(), Xr.size());
+        index_upload_subgraph(idx);
         up(idx->cent_dev, cent.data(), sizeof(float) * cent.size());
         up(idx->EV_dev, EV.data(), sizeof(float) * EV.size());
         up(idx->EVn_dev, EVn.data(), sizeof(float) * EVn.size());
-        up(idx->EVid_dev, bids.data(), sizeof(int32_t) * bids.size());
+        up(idx->EVid_dev, dev_ids.data(), sizeof(int32_t) * dev_ids.size());
         if (p.pivot_dtype == PA_FP8E4M3) {
             std::vector<uint8_t> codes(EV.size());
             std::vector<float> scales(n_p);
@@ -230,8 +256,7 @@ pa_status pa_index_load(pa_index* idx, const char* path) {
             up(idx->EVs_dev, scales.data(), sizeof(float) * scales.size());
         }
         idx->V = std::move(V);
-        idx->sub_adj = std::move(sub);
-        idx->R_sub = h.R_sub;
+        idx->xr_rows = h.xr_rows;
         idx->centroids = std::move(cent);
         idx->bucket_ids = std::move(bids);
         idx->n_b = h.n_b;

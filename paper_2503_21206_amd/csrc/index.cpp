@@ -41,23 +41,10 @@ void ensure_events(pa_index* idx, size_t n) {
 
 void project_all(pa_index* idx) {
     const int D = idx->p.dim, d_r = idx->p.d_r;
-    const size_t es = dtype_size(idx->p.xr_dtype);
-    idx->Xr_dev.ensure(static_cast<size_t>(idx->N) * d_r * es, idx->hbm_used, idx->p.hbm_budget);
     idx->V_dev.ensure(sizeof(float) * D * d_r, idx->hbm_used, idx->p.hbm_budget);
     PA_HIP(hipMemcpy(idx->V_dev.p, idx->V.data(), sizeof(float) * D * d_r, hipMemcpyHostToDevice));
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(idx->N, (int64_t{256} << 20) / (4 * D)));
-    DevBuf stage;
-    int64_t dummy = 0;
-    stage.ensure(sizeof(float) * chunk * D, dummy, 0);
-    for (int64_t r0 = 0; r0 < idx->N; r0 += chunk) {
-        const int64_t rows = std::min(chunk, idx->N - r0);
-        PA_HIP(hipMemcpyAsync(stage.p, idx->X + r0 * D, sizeof(float) * rows * D, hipMemcpyHostToDevice, idx->stream));
-        launch_project(static_cast<const float*>(stage.p), rows, D, static_cast<const float*>(idx->V_dev.p), d_r,
-                       static_cast<char*>(idx->Xr_dev.p) + static_cast<size_t>(r0) * d_r * es, idx->p.xr_dtype,
-                       nullptr, 0, nullptr, idx->stream);
-        PA_HIP(hipStreamSynchronize(idx->stream));
-    }
     idx->has_proj = true;
+    index_write_rows(idx);
 }
 
 void ensure_pool(pa_index* idx, int threads) {
@@ -90,6 +77,69 @@ void index_select_entries(const pa_index* idx, const float* Qr, const int32_t* c
                               static_cast<const float*>(idx->EVn_dev.p), static_cast<const int32_t*>(idx->EVid_dev.p),
                               r, idx->n_b, E, idx->p.metric, ids, dists, scratch, s);
     }
+}
+
+int32_t index_device_id(const pa_index* idx, int32_t node) {
+    if (!index_compact(idx)) return node;
+    const auto it = std::lower_bound(idx->cid.begin(), idx->cid.end(), node);
+    return (it != idx->cid.end() && *it == node) ? static_cast<int32_t>(it - idx->cid.begin()) : -1;
+}
+
+void index_write_rows(pa_index* idx) {
+    const int D = idx->p.dim, d_r = idx->p.d_r;
+    const size_t es = dtype_size(idx->p.xr_dtype);
+    const bool compact = index_compact(idx);
+    idx->xr_rows = 0;
+    if (!idx->has_proj || (compact && !idx->has_sub)) return;  // compact rows wait for the sample
+    const int64_t n = compact ? static_cast<int64_t>(idx->cid.size()) : idx->N;
+    idx->Xr_dev.ensure(std::max<size_t>(16, static_cast<size_t>(n) * d_r * es), idx->hbm_used, idx->p.hbm_budget);
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(n, 1), (int64_t{256} << 20) / (4 * D)));
+    DevBuf stage;
+    int64_t dummy = 0;
+    stage.ensure(sizeof(float) * chunk * D, dummy, 0);
+    std::vector<float> gathered(compact ? static_cast<size_t>(chunk) * D : 0);
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t rows = std::min(chunk, n - r0);
+        const float* src = idx->X + r0 * D;
+        if (compact) {  // the sampled rows, in device-id order
+            for (int64_t i = 0; i < rows; ++i)
+                std::memcpy(&gathered[static_cast<size_t>(i) * D], idx->X + static_cast<int64_t>(idx->cid[r0 + i]) * D,
+                            sizeof(float) * D);
+            src = gathered.data();
+        }
+        PA_HIP(hipMemcpyAsync(stage.p, src, sizeof(float) * rows * D, hipMemcpyHostToDevice, idx->stream));
+        launch_project(static_cast<const float*>(stage.p), rows, D, static_cast<const float*>(idx->V_dev.p), d_r,
+                       static_cast<char*>(idx->Xr_dev.p) + static_cast<size_t>(r0) * d_r * es, idx->p.xr_dtype,
+                       nullptr, 0, nullptr, idx->stream);
+        PA_HIP(hipStreamSynchronize(idx->stream));
+    }
+    idx->xr_rows = n;
+}
+
+void index_upload_subgraph(pa_index* idx) {
+    const int R = idx->R_sub;
+    if (!index_compact(idx)) {
+        idx->adj_dev.ensure(sizeof(int32_t) * idx->sub_adj.size(), idx->hbm_used, idx->p.hbm_budget);
+        PA_HIP(hipMemcpy(idx->adj_dev.p, idx->sub_adj.data(), sizeof(int32_t) * idx->sub_adj.size(),
+                         hipMemcpyHostToDevice));
+        return;
+    }
+    const int64_t n = static_cast<int64_t>(idx->cid.size());
+    std::vector<int32_t> pos(static_cast<size_t>(idx->N), -1);
+    for (int64_t i = 0; i < n; ++i) pos[idx->cid[i]] = static_cast<int32_t>(i);
+    std::vector<int32_t> adj(static_cast<size_t>(std::max<int64_t>(n, 1)) * R, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t* row = &idx->sub_adj[static_cast<size_t>(idx->cid[i]) * R];
+        for (int j = 0; j < R; ++j) {
+            if (row[j] < 0) continue;
+            require(pos[row[j]] >= 0, "subgraph edge into a node outside the sample");
+            adj[static_cast<size_t>(i) * R + j] = pos[row[j]];
+        }
+    }
+    idx->adj_dev.ensure(sizeof(int32_t) * adj.size(), idx->hbm_used, idx->p.hbm_budget);
+    PA_HIP(hipMemcpy(idx->adj_dev.p, adj.data(), sizeof(int32_t) * adj.size(), hipMemcpyHostToDevice));
+    idx->cid_dev.ensure(sizeof(int32_t) * std::max<int64_t>(n, 1), idx->hbm_used, idx->p.hbm_budget);
+    if (n > 0) PA_HIP(hipMemcpy(idx->cid_dev.p, idx->cid.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
 }
 
 namespace {
@@ -177,10 +227,10 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
         index_select_entries(idx, qr_dev + b0 * d_r, cl_dev + b0, nb, E, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev, s);
         PA_HIP(hipEventRecord(ev[1], s));
         if (gpu_stage) {
-            launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->N,
+            launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
                         static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, eid_dev + b0 * E, E, ef,
                         idx->p.metric, o.cache_log2, bid_dev + b0 * ef, bd_dev + b0 * ef, cnt_dev + b0 * 4, s,
-                        nullptr, o.visited);
+                        nullptr, o.visited, index_out_map(idx));
             PA_HIP(hipEventRecord(ev[2], s));
             PA_HIP(hipMemcpyAsync(beam_pin + b0 * ef, bid_dev + b0 * ef, sizeof(int32_t) * nb * ef,
                                   hipMemcpyDeviceToHost, s));
@@ -211,7 +261,10 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
                 host_stages_one(ctx, Q + i * D, beam_pin + i * ef, handoff, ef_cpu, k, refine_steps, idx->vis[w],
                                 idx->lists[w], out_ids + i * k, out_d + i * k, sc[i]);
             } else {
-                host_search_one(ctx, Q + i * D, ent_pin + i * E, E, ef_cpu, k, idx->vis[w], idx->lists[w],
+                int32_t* ent = ent_pin + i * E;
+                if (index_compact(idx))  // FES lists device ids
+                    for (int e = 0; e < E; ++e) ent[e] = ent[e] >= 0 ? idx->cid[ent[e]] : -1;
+                host_search_one(ctx, Q + i * D, ent, E, ef_cpu, k, idx->vis[w], idx->lists[w],
                                 out_ids + i * k, out_d + i * k, sc[i]);
             }
         });
@@ -274,6 +327,7 @@ pa_status pa_index_create(const pa_params* params, pa_index** out) {
         require(p.pivot_dtype == PA_F32 || p.pivot_dtype == PA_FP8E4M3, "pivot_dtype must be PA_F32 or PA_FP8E4M3");
         require(p.pivot_dtype != PA_FP8E4M3 || p.d_r % 32 == 0, "FP8 pivots need d_r % 32 == 0");
         require(p.preselect >= 0 && p.preselect <= 64, "preselect must be in [0, 64]");
+        require(p.compact == 0 || p.compact == 1, "compact must be 0 or 1");
         auto idx = std::make_unique<pa_index>();
         idx->p = p;
         PA_HIP(hipSetDevice(p.device));
@@ -310,6 +364,8 @@ pa_status pa_index_set_data(pa_index* idx, const float* X_host, int64_t N, const
         idx->N = N;
         idx->has_data = true;
         idx->has_proj = idx->has_sub = idx->has_entries = false;
+        idx->cid.clear();
+        idx->xr_rows = 0;
         idx->pool.reset();
     });
 }
@@ -361,11 +417,14 @@ pa_status pa_index_build_subgraph(pa_index* idx, const uint8_t* mask_host, const
         check_subgraph(idx->N, rowptr_host, nbrs_host, mask_host, R);
         idx->sub_adj = pad_rows(idx->N, rowptr_host, nbrs_host, R);
         idx->R_sub = R;
-        idx->adj_dev.ensure(sizeof(int32_t) * idx->sub_adj.size(), idx->hbm_used, idx->p.hbm_budget);
-        PA_HIP(hipMemcpy(idx->adj_dev.p, idx->sub_adj.data(), sizeof(int32_t) * idx->sub_adj.size(),
-                         hipMemcpyHostToDevice));
+        idx->cid.clear();
+        if (index_compact(idx))
+            for (int64_t u = 0; u < idx->N; ++u)
+                if (mask_host[u]) idx->cid.push_back(static_cast<int32_t>(u));
+        index_upload_subgraph(idx);
         idx->has_sub = true;
         idx->has_entries = false;
+        if (index_compact(idx)) index_write_rows(idx);  // the sampled rows of X_r
     });
 }
 
@@ -422,7 +481,9 @@ pa_status pa_index_build_entries(pa_index* idx, const int32_t* pivot_ids_host, i
         idx->cent_dev.ensure(sizeof(float) * idx->centroids.size(), idx->hbm_used, idx->p.hbm_budget);
         PA_HIP(hipMemcpy(idx->EV_dev.p, EV.data(), sizeof(float) * EV.size(), hipMemcpyHostToDevice));
         PA_HIP(hipMemcpy(idx->EVn_dev.p, EVn.data(), sizeof(float) * EVn.size(), hipMemcpyHostToDevice));
-        PA_HIP(hipMemcpy(idx->EVid_dev.p, idx->bucket_ids.data(), sizeof(int32_t) * n_p, hipMemcpyHostToDevice));
+        std::vector<int32_t> dev_ids(idx->bucket_ids);
+        for (auto& v : dev_ids) v = index_device_id(idx, v);  // pivots are sampled nodes
+        PA_HIP(hipMemcpy(idx->EVid_dev.p, dev_ids.data(), sizeof(int32_t) * n_p, hipMemcpyHostToDevice));
         PA_HIP(hipMemcpy(idx->cent_dev.p, idx->centroids.data(), sizeof(float) * idx->centroids.size(),
                          hipMemcpyHostToDevice));
         if (idx->p.pivot_dtype == PA_FP8E4M3) {

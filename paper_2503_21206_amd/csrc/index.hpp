@@ -66,6 +66,8 @@ struct pa_index {
     int R_full = 0;
     std::vector<int32_t> sub_adj;
     int R_sub = 0;
+    std::vector<int32_t> cid;  // compact layout: device id -> node id (increasing)
+    int64_t xr_rows = 0;       // rows of X_r and of the device adjacency
     std::vector<float> V;
     std::vector<int32_t> bucket_ids;
     std::vector<float> centroids;
@@ -73,7 +75,7 @@ struct pa_index {
     bool has_data = false, has_proj = false, has_sub = false, has_entries = false;
 
     int64_t hbm_used = 0;
-    pa::DevBuf V_dev, Xr_dev, adj_dev, cent_dev, EV_dev, EVn_dev, EVid_dev, EV8_dev, EVs_dev;
+    pa::DevBuf V_dev, Xr_dev, adj_dev, cent_dev, EV_dev, EVn_dev, EVid_dev, EV8_dev, EVs_dev, cid_dev;
     pa::DevBuf w_q, w_qr, w_cl, w_eid, w_ed, w_bid, w_bd, w_cnt, w_scr;
     pa::PinBuf p_q, p_beam, p_cnt, p_ent;
     hipStream_t stream = nullptr;
@@ -90,6 +92,16 @@ struct pa_index {
 };
 
 namespace pa {
+// Compact layout: device ids are positions in idx->cid; these map between the id spaces.
+inline bool index_compact(const pa_index* idx) { return idx->p.compact != 0; }
+inline const int32_t* index_out_map(const pa_index* idx) {
+    return index_compact(idx) ? static_cast<const int32_t*>(idx->cid_dev.p) : nullptr;
+}
+int32_t index_device_id(const pa_index* idx, int32_t node);  // -1 if not held on the device
+// (Re)writes X_r (all rows, or the sampled rows of the compact layout) from X and V.
+void index_write_rows(pa_index* idx);
+// Uploads the device adjacency (and the id map of the compact layout) from sub_adj.
+void index_upload_subgraph(pa_index* idx);
 // Entry selection for m reduced queries with the index's tables (fp32 or FP8 form).
 void index_select_entries(const pa_index* idx, const float* Qr, const int32_t* cluster, int64_t m, int E,
                           int32_t* ids, float* dists, int32_t* scratch, hipStream_t s);

@@ -163,6 +163,7 @@ struct BeamArgs {
     int cpr;     // 16-byte chunks per reduced row
     int wave_bytes;
     int bloom;  // 1: the visited set is the Bloom filter described above
+    const int32_t* out_map;  // optional: the id written out for row id v is out_map[v]
     int32_t* out_ids;
     float* out_d;
     int32_t* counters;
@@ -663,7 +664,8 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         const int t = wi * 64 + lane;
         if (t < a.ef) {
             if (t < w.size) {
-                oi[t] = static_cast<int32_t>(key_id(w.c[wi]));
+                const uint32_t v = key_id(w.c[wi]);
+                oi[t] = a.out_map ? a.out_map[v] : static_cast<int32_t>(v);
                 od[t] = unord_f32(static_cast<uint32_t>(w.c[wi] >> 32));
             } else {
                 oi[t] = -1;
@@ -724,10 +726,11 @@ int beam_auto_cache_log2(int ef, int R) {
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
-                 const int32_t* efq, int visited) {
+                 const int32_t* efq, int visited, const int32_t* out_map) {
     if (m == 0) return;
     BeamArgs a{};
     a.efq = efq;
+    a.out_map = out_map;
     a.bloom = visited == PA_VISITED_BLOOM ? 1 : 0;
     a.qr = Qr;
     a.m = m;

@@ -125,10 +125,11 @@ void launch_slot(pa_server* s, Slot& sl) {
     index_select_entries(idx, static_cast<const float*>(sl.qr.p), static_cast<const int32_t*>(sl.cl.p), m, E,
                          static_cast<int32_t*>(sl.eid.p), static_cast<float*>(sl.ed.p), static_cast<int32_t*>(sl.scr.p),
                          st);
-    launch_beam(static_cast<const float*>(sl.qr.p), m, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->N,
+    launch_beam(static_cast<const float*>(sl.qr.p), m, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
                 static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, static_cast<const int32_t*>(sl.eid.p), E, ef,
                 idx->p.metric, 0, static_cast<int32_t*>(sl.bid.p), static_cast<float*>(sl.bd.p),
-                static_cast<int32_t*>(sl.cnt.p), st, static_cast<const int32_t*>(sl.efq.p));
+                static_cast<int32_t*>(sl.cnt.p), st, static_cast<const int32_t*>(sl.efq.p), PA_VISITED_EXACT,
+                index_out_map(idx));
     PA_HIP(hipMemcpyAsync(sl.beam_pin.p, sl.bid.p, sizeof(int32_t) * m * ef, hipMemcpyDeviceToHost, st));
     PA_HIP(hipEventRecord(sl.done, st));
 }

@@ -305,6 +305,60 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     idx.close()
 
 
+def test_compact_layout_matches_full_layout(dev, tiny, tmp_path):
+    say("Index with X_r and the subgraph for the sampled nodes only, against the full layout")
+    s = tiny["spec"]
+    Q = tiny["Q"]
+    out = {}
+    for compact in (False, True):
+        idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f16", r=s.r, threads=4,
+                                      compact=compact))
+        idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+        if compact:  # the subgraph first: the rows are written when the projection arrives
+            idx.build_subgraph(tiny["mask"], tiny["sr"], tiny["sn"])
+            assert idx.info()["xr_rows"] == 0
+            idx.set_projection(tiny["V32"])
+        else:
+            idx.set_projection(tiny["V32"])
+            idx.build_subgraph(tiny["mask"], tiny["sr"], tiny["sn"])
+        idx.build_entries(tiny["pivots"], tiny["init"], 10)
+        info = idx.info()
+        ids, d, cnt, _ = idx.search(Q, 10, 64, 64, with_counters=True, batch=300)
+        ids0, d0, _, _ = idx.search(Q[:200], 10, 64, 64, stage_mask=2)  # GPU stage off: FES ids on the host
+        idsb, _, _, _ = idx.search(Q, 10, 64, 64, batch=300, bloom=True)
+        out[compact] = dict(info=info, ids=ids, d=d, cnt=cnt, ids0=ids0, d0=d0, idsb=idsb)
+        if compact:
+            path = str(tmp_path / "compact.pidx")
+            idx.save(path)
+            idx2 = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f16", r=s.r,
+                                           threads=4, compact=True))
+            idx2.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+            idx2.load(path)
+            assert idx2.info()["xr_rows"] == info["xr_rows"]
+            i2, d2, _, _ = idx2.search(Q, 10, 64, 64, batch=300)
+            assert (i2 == ids).all() and (d2.view(np.uint32) == d.view(np.uint32)).all()
+            idx2.close()
+            with pytest.raises(pa.PilotannError):  # a full-layout index refuses a compact checkpoint
+                idx3 = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f16", r=s.r))
+                idx3.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+                idx3.load(path)
+        idx.close()
+    full, comp = out[False], out[True]
+    n_s = int(tiny["mask"].sum())
+    say(f"  rows on the device {full['info']['xr_rows']} -> {comp['info']['xr_rows']}, "
+        f"HBM {full['info']['hbm_bytes']} -> {comp['info']['hbm_bytes']} bytes")
+    assert full["info"]["xr_rows"] == tiny["X"].shape[0] and comp["info"]["xr_rows"] == n_s
+    assert comp["info"]["hbm_bytes"] < full["info"]["hbm_bytes"]
+    # device ids keep the node order, so every decision and every result is the same
+    assert (comp["ids"] == full["ids"]).all() and (comp["d"].view(np.uint32) == full["d"].view(np.uint32)).all()
+    assert (comp["cnt"][:, 0] == full["cnt"][:, 0]).all()
+    assert (comp["ids0"] == full["ids0"]).all() and (comp["d0"].view(np.uint32) == full["d0"].view(np.uint32)).all()
+    gt, _ = oracle.exact_knn(tiny["X"], Q, 10)
+    rb_full, rb_comp = oracle.recall_at_k(full["idsb"], gt, 10), oracle.recall_at_k(comp["idsb"], gt, 10)
+    say(f"  Bloom filter (hashes of node ids vs device ids): recall {rb_full:.4f} vs {rb_comp:.4f}")
+    assert abs(rb_full - rb_comp) <= 0.01
+
+
 # ------------------------------------------------------------ large buckets and the FP8 form
 
 def _big_bucket_tables(tiny, n_p=4096, r=2):
