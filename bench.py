@@ -89,10 +89,11 @@ def build_fixture(spec, device):
                 build_subgraph_csr=build_subgraph_csr, device=device)
 
 
-def build_index(spec, fx, xr_dtype, shared):
+def build_index(spec, fx, xr_dtype, shared, compact=False):
     import paper_2503_21206_amd as pa
     t = time.time()
-    idx = pa.Index(pa.IndexConfig(dim=spec.dim, d_r=spec.d_r, metric=spec.metric, xr_dtype=xr_dtype, r=spec.r))
+    idx = pa.Index(pa.IndexConfig(dim=spec.dim, d_r=spec.d_r, metric=spec.metric, xr_dtype=xr_dtype, r=spec.r,
+                                  compact=compact))
     idx.set_data(fx["X"], fx["rp"], fx["nb"])
     if "V" not in shared:
         idx.fit_projection()
@@ -341,6 +342,28 @@ def roofline(spec, agg, steps, ef, E, xr_bytes, form):
             "launches": int(launches)}
 
 
+def memory_leg(spec, fx, shared, ef, full_info, steps):
+    """Memory-bounded layout (X_r and the device subgraph for the sampled nodes only, fp16
+    rows) at several sampling ratios: HBM held by the index, QPS and recall at ef."""
+    import dataclasses
+    out = {"what": "compact layout, fp16 X_r, ef_gpu/ef_cpu as timed; hbm_bytes = index tables and search "
+                   "buffers on the device",
+           "full_layout_rho_0.25": {"hbm_bytes": full_info["hbm_bytes"], "xr_rows": full_info["xr_rows"]},
+           "points": []}
+    for rho in (0.1, 0.25, 0.5, 0.75):
+        sp = dataclasses.replace(spec, rho=rho)
+        sh = {"V": shared["V"]} if rho != spec.rho else shared
+        idx = build_index(sp, fx, "f16", sh, compact=True)
+        dt, agg, rec = timed(idx, sp, fx, ef, steps, 1)
+        info = idx.info()
+        out["points"].append({"rho": rho, "hbm_bytes": info["hbm_bytes"], "xr_rows": info["xr_rows"],
+                              "qps": round(sp.queries * steps / dt, 1), "recall": round(rec, 5),
+                              "mean_n_dist3": round(agg["n_dist3"] / (sp.queries * steps), 1)})
+        log(f"  compact rho={rho}: {out['points'][-1]}")
+        idx.close()
+    return out
+
+
 def cpu_baseline(spec, fx, shared, ef_pair, budget_s):
     """The oracle's full pipeline, single process, on a bounded sample of queries."""
     import oracle
@@ -511,6 +534,9 @@ def main():
             extra["ablation"] = ablation(idx, spec, fx, ef)
             log("top-100")
             extra["top100"] = top100(idx, spec, fx, args.target)
+        if form == "f16" and not args.no_extra:
+            log("memory-bounded layout")
+            extra["memory_bounded"] = memory_leg(spec, fx, shared, ef, idx.info(), max(1, min(args.steps, 3)))
         if form == "f16" and args.serve_rates:
             rates = [float(x) for x in args.serve_rates.split(",") if x]
             serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
