@@ -388,7 +388,11 @@ typedef struct {
     int32_t ef_cpu;       /* stage-2/3 list size                                   */
     int32_t E;            /* entries per query (0: min(ef_gpu, n_p / r))           */
     int32_t batch;        /* queries per pipelined sub-batch (0: 16,384)           */
-    int32_t stage_mask;   /* bit 0 GPU stage, bit 1 refinement (0: both)           */
+    int32_t stage_mask;   /* bit 0 GPU stage, bit 1 refinement (0: both); bit 2 set
+                             skips the final traversal (needs the GPU stage): the
+                             output is the best k of the stage-2 list, so with a
+                             subgraph of every node and d_r = D the GPU alone finds
+                             the candidates (the paper's GPU-only special case)    */
     int32_t cache_log2;   /* GPU visited-cache size (0: automatic)                 */
     int32_t threads;      /* host threads (0: index default)                       */
     int32_t handoff;      /* stage-1 candidates handed to stage 2 per query, the

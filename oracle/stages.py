@@ -62,11 +62,16 @@ def final_traversal(q, X, rowptr, nbrs, cand_ids, cand_dists, visited, ef_cpu: i
 
 def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets, pivot_vecs,
              pivot_ids, *, k: int, ef_gpu: int, ef_cpu: int, E: int, metric: str = "l2",
-             refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True, bloom_log2=None):
+             refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True, bloom_log2=None,
+             use_final: bool = True):
     """All stages for every query; returns (ids [m][k], dists [m][k], counters [m][4]).
 
     counters = (stage-1 distances, stage-2 distances, stage-3 distances, stage-3 steps).
+    use_final=False skips stage 3 and returns the best k of the stage-2 list by full
+    distance (with every node sampled and d_r = D this is the GPU-only special case).
     """
+    if not use_final and not use_gpu_stage:
+        raise ValueError("without the GPU stage the final traversal must run")
     Q = np.asarray(Q, dtype=np.float64)
     Qr = project(Q, V)
     entries, _, _, _ = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
@@ -87,7 +92,15 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
                 c_d = as_f32(delta_many(Q[i], X[c_ids], metric)) if c_ids.size else np.zeros(0)
                 counters[i, 1] = c_ids.size
                 vis = set(int(v) for v in c_ids)
-            ids, d, f = final_traversal(Q[i], X, rowptr, nbrs, c_ids, c_d, vis, ef_cpu, k, metric)
+            if use_final:
+                ids, d, f = final_traversal(Q[i], X, rowptr, nbrs, c_ids, c_d, vis, ef_cpu, k, metric)
+            else:
+                order = sorted(range(len(c_ids)), key=lambda j: (float(c_d[j]), int(c_ids[j])))[:min(ef_cpu, k)]
+                ids = np.full(k, -1, dtype=np.int64)
+                d = np.full(k, np.inf)
+                ids[:len(order)] = [int(c_ids[j]) for j in order]
+                d[:len(order)] = [float(c_d[j]) for j in order]
+                f = {"n_dist": 0, "n_exp": 0}
         else:
             ef = max(ef_cpu, k)
             f = greedy_search(Q[i], X, rowptr, nbrs, ef, entries[i], metric)

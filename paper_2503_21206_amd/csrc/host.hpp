@@ -91,10 +91,11 @@ struct StageContext {
 };
 
 // Stage 2 + stage 3 for one query.  beam: stage-1 ids (n_beam, -1 skipped).
-// refine_steps < 0 skips the subgraph steps of stage 2 (candidates are still re-scored).
+// refine_steps < 0 skips the subgraph steps of stage 2 (candidates are still re-scored);
+// final_stage false skips stage 3 (the output is the best k of the stage-2 list).
 void host_stages_one(const StageContext& ctx, const float* q, const int32_t* beam, int n_beam,
                      int ef_cpu, int k, int refine_steps, Visited& vis, std::vector<Cand>& C,
-                     int64_t* out_ids, float* out_d, StageCounters& cnt);
+                     int64_t* out_ids, float* out_d, StageCounters& cnt, bool final_stage = true);
 
 // Plain Algorithm 1 on the full graph from entries (stage 3 alone).
 void host_search_one(const StageContext& ctx, const float* q, const int32_t* entries, int E, int ef,

@@ -286,7 +286,7 @@ void Visited::next_epoch() {
 
 void host_stages_one(const StageContext& ctx, const float* qf, const int32_t* beam, int n_beam, int ef_cpu,
                      int k, int refine_steps, Visited& vis, std::vector<Cand>& C, int64_t* out_ids,
-                     float* out_d, StageCounters& cnt) {
+                     float* out_d, StageCounters& cnt, bool final_stage) {
     vis.next_epoch();
     C.clear();
     const double* q = widen_query(qf, ctx.D);
@@ -308,6 +308,10 @@ void host_stages_one(const StageContext& ctx, const float* qf, const int32_t* be
     if (static_cast<int>(C.size()) > ef_cpu) C.resize(static_cast<size_t>(ef_cpu));
     // stage 2: refinement steps on the subgraph
     if (refine_steps > 0) run_steps(ctx, ctx.sub, q, ef_cpu, refine_steps, vis, C, cnt.dist2);
+    if (!final_stage) {
+        emit_topk(C, k, out_ids, out_d);
+        return;
+    }
     // stage 3: Algorithm 1 on the full graph, candidates unchecked, visited kept
     for (auto& c : C) c.checked = false;
     const int ef = std::max(ef_cpu, k);

@@ -165,8 +165,11 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     require(E >= 1 && E <= PA_MAX_EF, "E must be in [1, 512]");
     require(o.visited == PA_VISITED_EXACT || o.visited == PA_VISITED_BLOOM, "visited must be exact (0) or bloom (1)");
     const int mask = o.stage_mask == 0 ? 3 : o.stage_mask;
+    require(mask >= 1 && mask <= 7, "stage_mask must be in [0, 7]");
     const bool gpu_stage = (mask & 1) != 0;
     const int refine_steps = (mask & 2) ? idx->p.refine_steps : -1;
+    const bool final_stage = (mask & 4) == 0;
+    require(gpu_stage || final_stage, "without the GPU stage the final traversal must run");
     if (stats) *stats = pa_search_stats{};
     if (m == 0) return;
     require(Q && out_ids && out_d, "null pointer");
@@ -259,7 +262,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
             const int64_t i = b0 + j;
             if (gpu_stage) {
                 host_stages_one(ctx, Q + i * D, beam_pin + i * ef, handoff, ef_cpu, k, refine_steps, idx->vis[w],
-                                idx->lists[w], out_ids + i * k, out_d + i * k, sc[i]);
+                                idx->lists[w], out_ids + i * k, out_d + i * k, sc[i], final_stage);
             } else {
                 int32_t* ent = ent_pin + i * E;
                 if (index_compact(idx))  // FES lists device ids

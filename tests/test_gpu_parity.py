@@ -359,6 +359,44 @@ def test_compact_layout_matches_full_layout(dev, tiny, tmp_path):
     assert abs(rb_full - rb_comp) <= 0.01
 
 
+def test_gpu_only_special_case(dev, tiny):
+    say("GPU-only special case: every node sampled, d_r = D, no final traversal; against the oracle")
+    s = tiny["spec"]
+    X, Q = tiny["X"], tiny["Q"][:300]
+    D = X.shape[1]
+    V64, _, _ = oracle.fit_projection(X, D, s.metric)
+    V32 = V64.astype(np.float32)
+    Xr = oracle.project(X, V32).astype(np.float32)
+    full = np.ones(X.shape[0], dtype=np.uint8)
+    pivots = tiny["pivots"]
+    idx = pa.Index(pa.IndexConfig(dim=D, d_r=D, metric=s.metric, xr_dtype="f32", r=s.r, threads=4))
+    idx.set_data(X, tiny["rp"], tiny["nb"])
+    idx.set_projection(V32)
+    idx.build_subgraph(full, tiny["rp"], tiny["nb"])
+    idx.build_entries(pivots, tiny["init"], 10)
+    gt, _ = oracle.exact_knn(X, Q, 10)
+    P64 = Xr[pivots]
+    # the oracle clusters the same pivots from the same seeds
+    ob, oc = oracle.balanced_kmeans(P64.astype(np.float64), s.r, tiny["init"])
+    for mask, refine in ((5, False), (7, True)):
+        ids, d, cnt, _ = idx.search(Q, 10, 64, 64, stage_mask=mask, with_counters=True)
+        assert (cnt[:, 4] == 0).all() and (cnt[:, 0] > 0).all()
+        oi, od, _ = oracle.pipeline(Q, X, V32, tiny["rp"], tiny["nb"], tiny["rp"], tiny["nb"], Xr,
+                                    oc.astype(np.float32), ob, P64, pivots, k=10, ef_gpu=64, ef_cpu=64, E=8,
+                                    use_refine=refine, use_final=False)
+        same = np.mean([(ids[i] == oi[i]).all() for i in range(Q.shape[0])])
+        rec, orec = oracle.recall_at_k(ids, gt, 10), oracle.recall_at_k(oi, gt, 10)
+        say(f"  stage_mask {mask}: recall {rec:.4f} (oracle {orec:.4f}), {same:.3f} of lists equal")
+        assert same >= 0.97 and abs(rec - orec) <= 0.01
+        tally = DistTally()
+        for i in range(Q.shape[0]):
+            tally.check(d[i], oracle.as_f32(oracle.delta_many(Q[i], X[ids[i]])), i)
+        tally.done()
+    with pytest.raises(pa.PilotannError):  # the final traversal cannot be skipped without the GPU stage
+        idx.search(Q[:4], 10, 64, 64, stage_mask=6)
+    idx.close()
+
+
 # ------------------------------------------------------------ large buckets and the FP8 form
 
 def _big_bucket_tables(tiny, n_p=4096, r=2):

@@ -408,3 +408,23 @@ def test_graceful_degradation_is_plain_greedy_search_and_exact_at_large_ef():
     ids2, _, _ = oracle.pipeline(Q, X, V, rowptr, nbrs, rowptr, nbrs, Xr, c, b, Xr[P_ids], P_ids,
                                  k=10, ef_gpu=16, ef_cpu=n, E=8)
     assert (ids2 == gt).all()
+
+
+def test_gpu_only_special_case_is_exact_knn_with_every_node_and_full_rank():
+    # every node sampled (the subgraph is the full graph), d_r = D, and a list that holds
+    # every node: stage 1 alone finds all of them and the best k by full distance are the
+    # exact k nearest neighbours, with or without the refinement steps
+    X, rowptr, nbrs = _small_graph(seed=93)
+    n, D = X.shape
+    Q = gmm_points(94, 6, 10, 3, stream_offset=1)
+    V, _, _ = oracle.fit_projection(X, D)
+    Xr = oracle.project(X, V)
+    P_ids = np.arange(0, 64)
+    b, c = oracle.balanced_kmeans(Xr[P_ids], 2, [0, 1])
+    gt, gd = oracle.exact_knn(X, Q, 10)
+    for refine in (False, True):
+        ids, d, cnt = oracle.pipeline(Q, X, V, rowptr, nbrs, rowptr, nbrs, Xr, c, b, Xr[P_ids], P_ids,
+                                      k=10, ef_gpu=n, ef_cpu=n, E=8, use_refine=refine, use_final=False)
+        assert (ids == gt).all()
+        assert (d == gd.astype(np.float32).astype(np.float64)).all()
+        assert (cnt[:, 0] == n).all() and (cnt[:, 2] == 0).all()
