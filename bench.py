@@ -364,6 +364,31 @@ def memory_leg(spec, fx, shared, ef, full_info, steps):
     return out
 
 
+def ratio_sweep(spec, fx, shared, ef, steps):
+    """The paper's (rho, d_r / D) grid, compact layout with fp16 rows at a fixed ef: recall,
+    QPS and HBM per point (opt-in: nine index builds)."""
+    import dataclasses
+    subs, Vs, out = {}, {spec.d_r: shared["V"]}, []
+    for d_r in (32, 64, 128):
+        for rho in (0.1, 0.25, 0.5):
+            sp = dataclasses.replace(spec, rho=rho, d_r=d_r)
+            sh = dict(subs.get(rho, {}))
+            if d_r in Vs:
+                sh["V"] = Vs[d_r]
+            idx = build_index(sp, fx, "f16", sh, compact=True)
+            Vs[d_r] = sh["V"]
+            subs[rho] = {k: sh[k] for k in ("sub", "pivots", "init")}
+            dt, agg, rec = timed(idx, sp, fx, ef, steps, 1)
+            info = idx.info()
+            out.append({"rho": rho, "d_r": d_r, "recall": round(rec, 5), "qps": round(sp.queries * steps / dt, 1),
+                        "hbm_bytes": info["hbm_bytes"],
+                        "beam_ms_per_step": round(agg["beam_ms"] / steps, 3),
+                        "mean_n_dist3": round(agg["n_dist3"] / (sp.queries * steps), 1)})
+            log(f"  ratio sweep: {out[-1]}")
+            idx.close()
+    return {"what": f"compact layout, fp16 X_r, ef_gpu/ef_cpu = {ef}", "points": out}
+
+
 def gpu_only_leg(spec, fx, target, steps):
     """The paper's GPU-only special case: every node sampled (the subgraph is the full
     graph), d_r = D in fp32, stage 1 alone finds the candidates and the host only re-ranks
@@ -507,6 +532,7 @@ def main():
     ap.add_argument("--no-gemm", action="store_true", help="skip the MFMA kernel leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the ablation and top-100 legs")
     ap.add_argument("--no-bloom", action="store_true", help="skip the Bloom-filter leg of each form")
+    ap.add_argument("--ratio-sweep", action="store_true", help="add the (rho, d_r) grid (nine index builds)")
     ap.add_argument("--forms", default="f32,f16")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -583,6 +609,9 @@ def main():
             extra["top100"] = top100(idx, spec, fx, args.target)
             log("gpu-only special case")
             extra["gpu_only"] = gpu_only_leg(spec, fx, args.target, max(1, min(args.steps, 3)))
+        if form == "f16" and args.ratio_sweep:
+            log("ratio sweep")
+            extra["ratio_sweep"] = ratio_sweep(spec, fx, shared, ef, max(1, min(args.steps, 3)))
         if form == "f16" and not args.no_extra:
             log("memory-bounded layout")
             extra["memory_bounded"] = memory_leg(spec, fx, shared, ef, idx.info(), max(1, min(args.steps, 3)))

@@ -143,3 +143,28 @@ def test_server_rejects_bad_requests(dev, tiny, index):
         small.submit(q, 10, 64, 1)
     assert e.value.status == -4
     small.close()
+
+
+def test_server_on_the_compact_layout_matches_the_full_layout(dev, tiny, index):
+    s = tiny["spec"]
+    comp = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f32", r=s.r, threads=4,
+                                   compact=True))
+    comp.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+    comp.set_projection(tiny["V32"])
+    mask = comp.sample_nodes(node_order(s.n, s.seed), round(s.rho * s.n), s.sample_mode)
+    comp.build_subgraph(mask, tiny["sr"], tiny["sn"])
+    comp.build_entries(tiny["pivots"], tiny["init"], 10)
+    reqs = _requests(tiny, 60)
+    out = []
+    for idx in (index, comp):
+        srv = pa.Server(idx, hbm_budget=1 << 30, max_batch=32, streams=2, threads=4)
+        for tag, q, k, ef in reqs:
+            srv.submit(q, k, ef, tag)
+        srv.drain()
+        out.append({r["tag"]: r for r in srv.poll(1000)})
+        srv.close()
+    print("server: 60 requests on the full and on the compact layout", flush=True)
+    for tag, _, _, _ in reqs:
+        a, b = out[0][tag], out[1][tag]
+        assert (a["ids"] == b["ids"]).all() and (a["dists"].view(np.uint32) == b["dists"].view(np.uint32)).all()
+    comp.close()
