@@ -196,6 +196,32 @@ def test_traverse_bloom_filter_parity(dev, tiny):
         pa.gpu_traverse(Qr, Xr, adj, _t(ent[:4].astype(np.int32), dev), 256, bloom_log2=13)
 
 
+def test_traverse_exact_ties_and_near_ties(dev, tiny):
+    # every row repeated (equal distances: the id decides) and a copy nudged by one ulp
+    # (distances a few units apart in fp32): the plain scores cannot order these, so the
+    # steps are decided on exactly re-scored keys, and the lists must still be the oracle's
+    say("gpu_traverse on rows with exact duplicates and one-ulp neighbours, exact and Bloom visited sets")
+    base = tiny["Xr32"][:3000]
+    nudged = np.nextafter(base, np.float32(np.inf)).astype(np.float32)
+    Xr = np.concatenate([base, base, nudged]).astype(np.float32)
+    n = Xr.shape[0]
+    rng = np.random.default_rng(5)
+    R = 16
+    rows = []
+    for u in range(n):  # a random graph over the copies, with the copies of u linked
+        k = u % 3000
+        nb = set(rng.choice(n, R - 2, replace=False).tolist()) | {k, k + 3000}
+        nb.discard(u)
+        rows.append(sorted(nb)[:R])
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    nbrs = np.concatenate([np.asarray(r, dtype=np.int64) for r in rows])
+    w = dict(Qr32=tiny["Qr32"][:200], sr=rp, sn=nbrs, sub_adj=oracle.padded_from_csr(rp, nbrs, R))
+    ent = rng.choice(n, (200, 8)).astype(np.int64)
+    for bloom in (None, 16):
+        _traverse_check(dev, w, Xr, _t(Xr, dev), ent, 32, np.arange(200), bloom_log2=bloom)
+
+
 def test_traverse_f16_and_bf16(dev, tiny):
     ent, _, _, _ = oracle_entries(tiny, 8)
     for name, conv, tdt in (("f16", to_f16, torch.float16), ("bf16", to_bf16, torch.bfloat16)):
