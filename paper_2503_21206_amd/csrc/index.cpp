@@ -233,7 +233,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
             launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
                         static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, eid_dev + b0 * E, E, ef,
                         idx->p.metric, o.cache_log2, bid_dev + b0 * ef, bd_dev + b0 * ef, cnt_dev + b0 * 4, s,
-                        nullptr, o.visited, index_out_map(idx));
+                        nullptr, o.visited, index_out_map(idx), false);  // stage 2 reads only the ids
             PA_HIP(hipEventRecord(ev[2], s));
             PA_HIP(hipMemcpyAsync(beam_pin + b0 * ef, bid_dev + b0 * ef, sizeof(int32_t) * nb * ef,
                                   hipMemcpyDeviceToHost, s));

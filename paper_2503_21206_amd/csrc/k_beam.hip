@@ -34,9 +34,10 @@
 // order among the new candidates).  When some comparison involves closer keys, the
 // batch's candidates and the inexact entries of C are re-scored exactly (float-float:
 // the correctly rounded value, which any summation order also rounds to) and that step
-// is decided on exact keys; the entries left in C are re-scored exactly at the end,
-// before the output.  A re-scored key stays within the radius of its plain value, so C
-// stays sorted and every decision equals the exact one.  Inner products have no
+// is decided on exact keys.  A re-scored key stays within the radius of its plain value,
+// so C stays sorted and every decision equals the exact one; the list's order is exact at
+// the end, and its remaining plain values are re-scored exactly when the caller reads the
+// distances (the search pipeline reads only the ids).  Inner products have no
 // relative bound of this kind and are scored exactly at once.
 //
 // One loop step: find the first unchecked entry of C (one ballot per register), mark it
@@ -164,6 +165,7 @@ struct BeamArgs {
     int wave_bytes;
     int bloom;  // 1: the visited set is the Bloom filter described above
     const int32_t* out_map;  // optional: the id written out for row id v is out_map[v]
+    int exact_out;           // 0: the caller reads only the ids (and their order) of the output
     int32_t* out_ids;
     float* out_d;
     int32_t* counters;
@@ -656,7 +658,9 @@ __global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a
         const int mp = w.offer(v);
         lb = min(lb, mp);
     }
-    if (MET == PA_METRIC_L2) w.exactify_list();  // the output holds exact distances
+    // the list's order is already exact; its remaining plain values are re-scored only when
+    // the caller reads the distances
+    if (MET == PA_METRIC_L2 && a.exact_out) w.exactify_list();
     int32_t* oi = a.out_ids + qi * a.ef;
     float* od = a.out_d + qi * a.ef;
 #pragma unroll
@@ -726,11 +730,12 @@ int beam_auto_cache_log2(int ef, int R) {
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
-                 const int32_t* efq, int visited, const int32_t* out_map) {
+                 const int32_t* efq, int visited, const int32_t* out_map, bool exact_dists) {
     if (m == 0) return;
     BeamArgs a{};
     a.efq = efq;
     a.out_map = out_map;
+    a.exact_out = exact_dists ? 1 : 0;
     a.bloom = visited == PA_VISITED_BLOOM ? 1 : 0;
     a.qr = Qr;
     a.m = m;

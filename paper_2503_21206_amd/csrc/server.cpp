@@ -129,7 +129,7 @@ void launch_slot(pa_server* s, Slot& sl) {
                 static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, static_cast<const int32_t*>(sl.eid.p), E, ef,
                 idx->p.metric, 0, static_cast<int32_t*>(sl.bid.p), static_cast<float*>(sl.bd.p),
                 static_cast<int32_t*>(sl.cnt.p), st, static_cast<const int32_t*>(sl.efq.p), PA_VISITED_EXACT,
-                index_out_map(idx));
+                index_out_map(idx), false);  // the host stages read only the ids
     PA_HIP(hipMemcpyAsync(sl.beam_pin.p, sl.bid.p, sizeof(int32_t) * m * ef, hipMemcpyDeviceToHost, st));
     PA_HIP(hipEventRecord(sl.done, st));
 }
