@@ -291,22 +291,35 @@ struct Wave {
         atomicOr(&cache[b2 >> 5], 1u << (b2 & 31));
     }
 
-    // Test-and-set of v in the visited cache; true when v must be scored.
+    // Test-and-set of v in the visited cache; true when v must be scored.  The 2^hlog slots
+    // form buckets of 4: one 16-byte LDS read tests a bucket; v is visited if the bucket
+    // holds it; otherwise a free slot ends the search (v is stored there with a CAS, and a
+    // slot taken by another lane meanwhile means reading the bucket again), and a full
+    // bucket sends v on to the next one.  Slots are only ever cleared all at once, so the
+    // first bucket with a free slot is the last one that can hold v.
     __device__ bool test_and_set(int v, bool& stored) {
         stored = false;
         if (v < 0) return false;
-        uint32_t h = hash_slot(static_cast<uint32_t>(v), a.hlog);
+        const uint32_t u = static_cast<uint32_t>(v);
+        const uint32_t bmask = static_cast<uint32_t>(hmask) >> 2;
+        uint32_t b = hash_slot(u, a.hlog - 2);
 #pragma nounroll
         for (int p = 0; p < kProbes; ++p) {
-            const uint32_t old = atomicCAS(&cache[h], kEmpty, static_cast<uint32_t>(v));
+            const uint4 s = reinterpret_cast<const uint4*>(cache)[b];
+            if (s.x == u || s.y == u || s.z == u || s.w == u) return false;
+            const int e = s.x == kEmpty ? 0 : (s.y == kEmpty ? 1 : (s.z == kEmpty ? 2 : (s.w == kEmpty ? 3 : 4)));
+            if (e == 4) {
+                b = (b + 1) & bmask;
+                continue;
+            }
+            const uint32_t old = atomicCAS(&cache[b * 4 + e], kEmpty, u);
             if (old == kEmpty) {
                 stored = true;
                 return true;
             }
-            if (old == static_cast<uint32_t>(v)) return false;
-            h = (h + 1) & hmask;
+            if (old == u) return false;
         }
-        return true;  // cache neighbourhood full: score it (never a false "visited")
+        return true;  // no free slot nearby: score it (never a false "visited")
     }
 
     // Re-populate the cache with the ids currently in C after a reset.
