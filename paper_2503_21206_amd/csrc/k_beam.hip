@@ -522,7 +522,35 @@ struct Wave {
         int rank = 0;
         int shift[CH];
         int minpos = INT_MAX;
-        while (true) {
+        // Common case: the survivors take distinct positions in C.  Positions then order the
+        // survivors among themselves (two survivors whose keys are close enough to need a
+        // comparison share a position, or an entry of C between them is close to both and
+        // was caught above), so ranks and shifts are population counts of the occupied
+        // positions, flagged in tmp (the merge below rewrites it).
+        bool distinct = false;
+        {
+            uint32_t* flag = reinterpret_cast<uint32_t*>(tmp);
+            const bool mine = (surv >> lane) & 1ull;
+#pragma unroll
+            for (int w = 0; w < CH; ++w) flag[w * 64 + lane] = 0u;
+            wave_sync();
+            uint32_t before = 0;
+            if (mine) before = atomicAdd(&flag[pos], 1u);
+            wave_sync();
+            if (__ballot(mine && before != 0) == 0) {
+                distinct = true;
+                int below = 0;  // survivors placed before register w
+#pragma unroll
+                for (int w = 0; w < CH; ++w) {
+                    const uint64_t occ = __ballot(flag[w * 64 + lane] != 0);
+                    shift[w] = below + mbcnt(occ) + static_cast<int>((occ >> lane) & 1ull);
+                    if (mine && (pos >> 6) == w) rank = below + __popcll(occ & ((1ull << (pos & 63)) - 1));
+                    if (minpos == INT_MAX && occ != 0) minpos = w * 64 + __builtin_ctzll(occ);
+                    below += __popcll(occ);
+                }
+            }
+        }
+        while (!distinct) {
             const bool mine = (surv >> lane) & 1ull;
             rank = 0;
             minpos = INT_MAX;
@@ -583,11 +611,11 @@ struct Wave {
     }
 };
 
-// Small lists (CH <= 2) fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about
-// as many; only the fp32 variant with two registers and a run-time lane count spills a
-// few values); larger lists keep the compiler's choice.
+// One-register lists fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about as
+// many; only fp32 rows with a run-time lane count spill a few values), two-register lists
+// in 80 (6 waves); larger lists keep the compiler's choice.
 template <int DT, int MET, int CH, int GSL>
-__global__ __launch_bounds__(256, (CH <= 2 ? 7 : 1)) void beam_kernel(BeamArgs a) {
+__global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
