@@ -229,6 +229,25 @@ pa_status pa_gpu_traverse_bloom(const float* Qr_dev, int64_t m, int32_t d_r, con
                                 int32_t filter_log2, int32_t* ids_dev, float* d_dev,
                                 int32_t* counters_dev, void* stream);
 
+/* Options of pa_gpu_traverse_ex. */
+typedef struct {
+    int32_t visited;     /* PA_VISITED_EXACT or PA_VISITED_BLOOM                        */
+    int32_t cache_log2;  /* exact: 2^cache_log2 cache slots (8..13); Bloom: a filter of
+                            32 << cache_log2 bits; 0: automatic                          */
+    int32_t width;       /* entries of C expanded per step: 1 (Algorithm 1), or 2 (the
+                            first two unchecked entries together; needs R <= 32).  Width
+                            2 is not the paper's algorithm: it may expand a node that
+                            Algorithm 1 would have dropped from C first                 */
+} pa_traverse_opts;
+
+/* Stage 1 with options (opts NULL: exact, automatic, width 1 = pa_gpu_traverse).  As
+ * pa_gpu_traverse otherwise; with the Bloom filter as pa_gpu_traverse_bloom. */
+pa_status pa_gpu_traverse_ex(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
+                             int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
+                             const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
+                             const pa_traverse_opts* opts, int32_t* ids_dev, float* d_dev,
+                             int32_t* counters_dev, void* stream);
+
 /* Stage 1 with a list size per query, so that requests of uneven ef share one launch
  * (used by the serving loop).  As pa_gpu_traverse, plus ef_dev [m] int32 with
  * 1 <= ef_dev[i] <= ef_max: query i keeps a list of ef_dev[i] entries and uses the first
@@ -404,6 +423,8 @@ typedef struct {
     int32_t visited;      /* stage-1 visited set: PA_VISITED_EXACT (0) or
                              PA_VISITED_BLOOM (cache_log2 then sizes the filter:
                              32 << cache_log2 bits)                                 */
+    int32_t width;        /* stage-1 expansion width (0 or 1: Algorithm 1; 2: see
+                             pa_traverse_opts)                                       */
 } pa_search_opts;
 
 typedef struct {

@@ -29,10 +29,10 @@ from .projection import project
 from .traverse import greedy_search
 
 
-def gpu_stage(qr, Xr, sub_rowptr, sub_nbrs, entries, ef: int, metric: str = "l2", bloom_log2=None):
+def gpu_stage(qr, Xr, sub_rowptr, sub_nbrs, entries, ef: int, metric: str = "l2", bloom_log2=None, width: int = 1):
     """Stage 1 for one reduced query: Algorithm 1 on the subgraph (with the exact visited
     set, or the Bloom filter of section 4.3 when bloom_log2 is given)."""
-    return greedy_search(qr, Xr, sub_rowptr, sub_nbrs, ef, entries, metric, bloom_log2=bloom_log2)
+    return greedy_search(qr, Xr, sub_rowptr, sub_nbrs, ef, entries, metric, bloom_log2=bloom_log2, width=width)
 
 
 def refine(q, X, sub_rowptr, sub_nbrs, beam_ids, ef_cpu: int, metric: str = "l2", steps: int = 2):
@@ -63,7 +63,7 @@ def final_traversal(q, X, rowptr, nbrs, cand_ids, cand_dists, visited, ef_cpu: i
 def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets, pivot_vecs,
              pivot_ids, *, k: int, ef_gpu: int, ef_cpu: int, E: int, metric: str = "l2",
              refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True, bloom_log2=None,
-             use_final: bool = True):
+             use_final: bool = True, width: int = 1):
     """All stages for every query; returns (ids [m][k], dists [m][k], counters [m][4]).
 
     counters = (stage-1 distances, stage-2 distances, stage-3 distances, stage-3 steps).
@@ -81,7 +81,7 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
     counters = np.zeros((m, 4), dtype=np.int64)
     for i in range(m):
         if use_gpu_stage:
-            g = gpu_stage(Qr[i], Xr, sub_rowptr, sub_nbrs, entries[i], ef_gpu, metric, bloom_log2)
+            g = gpu_stage(Qr[i], Xr, sub_rowptr, sub_nbrs, entries[i], ef_gpu, metric, bloom_log2, width)
             counters[i, 0] = g["n_dist"]
             if use_refine:
                 r = refine(Q[i], X, sub_rowptr, sub_nbrs, g["ids"], ef_cpu, metric, refine_steps)

@@ -13,7 +13,10 @@ Readings where the paper is silent:
 * visited is an exact set, one distance per visited node, so
   n_dist = |visited|; ``bloom_log2`` selects the paper's lossy filter instead
   (section 4.3; its readings are in ``oracle.bloom``);
-* expansion width is one node per loop step, as printed;
+* expansion width is one node per loop step, as printed; ``width=2`` is a variant
+  (not the paper's): each step takes the first two unchecked entries of C, marks
+  both, and scores the unvisited out-neighbours of both (first node's row, then
+  the second's) as one group before the resize;
 * distances are single-precision values (section 6.1): each is computed exactly
   and rounded once to fp32 before it enters C (``precision="f64"`` keeps fp64).
 
@@ -49,7 +52,8 @@ def _resize_gap(sorted_keys, ef: int) -> float:
 
 
 def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "l2", *,
-                  initial=None, visited=None, max_steps=None, precision: str = "f32", bloom_log2=None):
+                  initial=None, visited=None, max_steps=None, precision: str = "f32", bloom_log2=None,
+                  width: int = 1):
     """Run Algorithm 1 for one query.
 
     q        query vector (any float dtype; used in fp64)
@@ -61,6 +65,8 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
     """
     if ef < 1:
         raise ValueError("ef must be >= 1")
+    if width not in (1, 2):
+        raise ValueError("width must be 1 or 2")
     if bloom_log2 is not None and (initial is not None or visited is not None):
         raise ValueError("the Bloom filter variant starts from entry points only")
     q = np.asarray(q, dtype=np.float64)
@@ -102,23 +108,25 @@ def greedy_search(q, vectors, rowptr, nbrs, ef: int, entries=(), metric: str = "
     del C[ef:]
     n_exp = 0
     while max_steps is None or n_exp < max_steps:
-        # line 5: the first unchecked node in C
-        pos = next((i for i, c in enumerate(C) if not c[1]), None)
-        if pos is None:
+        # line 5: the first unchecked node in C (the first `width` of them)
+        unchecked = [i for i, c in enumerate(C) if not c[1]][:width + 1]
+        if not unchecked:
             break  # line 12: no unchecked node left
-        nxt = next((i for i in range(pos + 1, len(C)) if not C[i][1]), None)
-        if nxt is not None:
-            margin = min(margin, _rel_gap(C[pos][0][0], C[nxt][0][0]))
-        C[pos][1] = True
-        u = C[pos][0][1]
-        n_exp += 1
+        chosen = unchecked[:width]
+        if len(unchecked) > width:  # which nodes are expanded: the last chosen vs the next
+            margin = min(margin, _rel_gap(C[chosen[-1]][0][0], C[unchecked[width]][0][0]))
+        group = []
+        for pos in chosen:
+            C[pos][1] = True
+            u = C[pos][0][1]
+            group.extend(int(v) for v in nbrs[rowptr[u]:rowptr[u + 1]])
+        n_exp += len(chosen)
         # lines 6-10: unvisited out-neighbours, mark, score, insert
         new = []
         if bloom is not None:
-            new = bloom.fresh_of_group(nbrs[rowptr[u]:rowptr[u + 1]])
+            new = bloom.fresh_of_group(group)
         else:
-            for v in nbrs[rowptr[u]:rowptr[u + 1]]:
-                v = int(v)
+            for v in group:
                 if v not in seen:
                     seen.add(v)
                     new.append(v)

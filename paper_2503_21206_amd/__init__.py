@@ -45,7 +45,11 @@ class Params(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("ef_gpu", C.c_int32), ("ef_cpu", C.c_int32), ("E", C.c_int32), ("batch", C.c_int32),
                 ("stage_mask", C.c_int32), ("cache_log2", C.c_int32), ("threads", C.c_int32),
-                ("handoff", C.c_int32), ("q_dev", C.c_void_p), ("visited", C.c_int32)]
+                ("handoff", C.c_int32), ("q_dev", C.c_void_p), ("visited", C.c_int32), ("width", C.c_int32)]
+
+
+class TraverseOpts(C.Structure):
+    _fields_ = [("visited", C.c_int32), ("cache_log2", C.c_int32), ("width", C.c_int32)]
 
 
 class SearchStats(C.Structure):
@@ -93,6 +97,7 @@ _SIGS = {
     "pa_gpu_traverse": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P],
     "pa_gpu_traverse_bloom": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
                               _P],
+    "pa_gpu_traverse_ex": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _P, _P],
     "pa_cpu_stages": [_P, _I64, _I32, _P, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _I32,
                       _P, _P, _P],
     "pa_cpu_search": [_P, _I64, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P],
@@ -338,9 +343,10 @@ def select_entries_fp8(Qr, cluster, EV, EV8, EVscale, EVnorm, EVid, E: int, K: i
 
 
 def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: int = 0, stream=None,
-                 bloom_log2: int = -1):
+                 bloom_log2: int = -1, width: int = 1):
     """Stage 1 on device tensors -> (ids [m][ef] int32, dists [m][ef] fp32, counters [m][4] int32).
-    bloom_log2 >= 0 selects the Bloom-filter visited set of 2^bloom_log2 bits (0: automatic)."""
+    bloom_log2 >= 0 selects the Bloom-filter visited set of 2^bloom_log2 bits (0: automatic);
+    width 2 expands the first two unchecked entries per step (pa_gpu_traverse_ex)."""
     import torch
     m, d_r = Qr.shape
     N, R = adj.shape
@@ -353,6 +359,14 @@ def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: 
     ids = torch.empty((m, ef), dtype=torch.int32, device=Qr.device)
     dist = torch.empty((m, ef), dtype=torch.float32, device=Qr.device)
     cnt = torch.empty((m, 4), dtype=torch.int32, device=Qr.device)
+    if width != 1:
+        cl = cache_log2 if bloom_log2 < 0 else (0 if bloom_log2 == 0 else bloom_log2 - 5)
+        opts = TraverseOpts(PA_VISITED_EXACT if bloom_log2 < 0 else PA_VISITED_BLOOM, cl, width)
+        _check(lib().pa_gpu_traverse_ex(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
+                                        _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E,
+                                        ef, METRICS[metric], C.byref(opts), _dev(ids), _dev(dist), _dev(cnt),
+                                        _stream(stream)))
+        return ids, dist, cnt
     fn = lib().pa_gpu_traverse if bloom_log2 < 0 else lib().pa_gpu_traverse_bloom
     _check(fn(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
               _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E, ef,
@@ -529,11 +543,11 @@ class Index:
 
     def search(self, Q, k: int, ef_gpu: int, ef_cpu: int = 0, E: int = 0, batch: int = 0, stage_mask: int = 0,
                cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0,
-               Q_dev=None, bloom: bool = False):
+               Q_dev=None, bloom: bool = False, width: int = 1):
         """Q_dev: optional torch tensor on the index's device holding the same [m][dim] fp32
         queries as Q; the GPU stage then reads them from HBM instead of uploading Q.
         bloom: stage 1 tracks visited nodes in the paper's Bloom filter (32 << cache_log2
-        bits) instead of the exact set."""
+        bits) instead of the exact set.  width 2: stage 1 expands two entries per step."""
         Q, pq = _host(Q, np.float32)
         m = Q.shape[0]
         if Q.ndim != 2 or Q.shape[1] != self.cfg.dim:
@@ -549,7 +563,8 @@ class Index:
         ids = np.empty((m, k), dtype=np.int64)
         dist = np.empty((m, k), dtype=np.float32)
         cnt = np.empty((m, 8), dtype=np.int32) if with_counters else None
-        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd, 1 if bloom else 0)
+        opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd, 1 if bloom else 0,
+                          width)
         st = SearchStats()
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))

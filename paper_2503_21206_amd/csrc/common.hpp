@@ -128,7 +128,7 @@ void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dty
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
                  const int32_t* efq = nullptr, int visited = PA_VISITED_EXACT,
-                 const int32_t* out_map = nullptr, bool exact_dists = true);
+                 const int32_t* out_map = nullptr, bool exact_dists = true, int width = 1);
 int beam_auto_cache_log2(int ef, int R);
 
 }  // namespace pa

@@ -164,6 +164,8 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     const int E = o.E > 0 ? o.E : std::min(o.ef_gpu, idx->n_b);
     require(E >= 1 && E <= PA_MAX_EF, "E must be in [1, 512]");
     require(o.visited == PA_VISITED_EXACT || o.visited == PA_VISITED_BLOOM, "visited must be exact (0) or bloom (1)");
+    const int width = o.width <= 1 ? 1 : o.width;
+    require(width == 1 || (width == 2 && idx->R_sub <= 32), "width must be 0, 1, or 2 with a subgraph degree <= 32");
     const int mask = o.stage_mask == 0 ? 3 : o.stage_mask;
     require(mask >= 1 && mask <= 7, "stage_mask must be in [0, 7]");
     const bool gpu_stage = (mask & 1) != 0;
@@ -233,7 +235,7 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
             launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
                         static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, eid_dev + b0 * E, E, ef,
                         idx->p.metric, o.cache_log2, bid_dev + b0 * ef, bd_dev + b0 * ef, cnt_dev + b0 * 4, s,
-                        nullptr, o.visited, index_out_map(idx), false);  // stage 2 reads only the ids
+                        nullptr, o.visited, index_out_map(idx), false, width);  // stage 2 reads only the ids
             PA_HIP(hipEventRecord(ev[2], s));
             PA_HIP(hipMemcpyAsync(beam_pin + b0 * ef, bid_dev + b0 * ef, sizeof(int32_t) * nb * ef,
                                   hipMemcpyDeviceToHost, s));

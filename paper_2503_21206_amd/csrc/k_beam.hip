@@ -18,6 +18,10 @@
 // evolves exactly as in Algorithm 1; only the count of distance evaluations can exceed
 // |visited| (reported per query together with the number of forget events).
 //
+// Expansion width 2 (an option; not in the paper): each step expands the first two
+// unchecked entries of C together, their adjacency rows filling the two halves of the
+// wavefront, which halves the number of steps and their fixed costs.
+//
 // The paper's own visited set is available as an option: a Bloom filter of 32 << hlog
 // bits in the same LDS words, two multiplicative hashes per id.  A node whose two bits
 // are set counts as visited, also when other nodes set them (a false positive: the node
@@ -166,6 +170,7 @@ struct BeamArgs {
     int bloom;  // 1: the visited set is the Bloom filter described above
     const int32_t* out_map;  // optional: the id written out for row id v is out_map[v]
     int exact_out;           // 0: the caller reads only the ids (and their order) of the output
+    int width;               // entries expanded per step: 1, or 2 (R <= 32)
     int32_t* out_ids;
     float* out_d;
     int32_t* counters;
@@ -268,6 +273,12 @@ struct Wave {
         for (int w = 0; w < CH; ++w)
             if (w == (t >> 6)) k = readlane64(c[w], t & 63);
         return k;
+    }
+
+    __device__ void mark_checked(int t) {  // t uniform, t < size
+#pragma unroll
+        for (int w = 0; w < CH; ++w)
+            if (w == (t >> 6) && lane == (t & 63)) c[w] |= kChecked;
     }
 
     __device__ void clear_cache() {
@@ -612,8 +623,8 @@ struct Wave {
 };
 
 // One-register lists fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about as
-// many; only fp32 rows with a run-time lane count spill a few values), two-register lists
-// in 80 (6 waves); larger lists keep the compiler's choice.
+// many), two-register lists in 80 (6 waves); only the variants with a run-time lane count
+// spill a few values.  Larger lists keep the compiler's choice.
 template <int DT, int MET, int CH, int GSL>
 __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -640,10 +651,23 @@ __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_k
     }
     int lb = 0;  // every position below lb holds a checked entry
     const int half = 1 << (a.hlog - 1);
-    // Speculation: the adjacency row of the unchecked entry after the one being expanded
-    // is loaded while the current step gathers and merges; the next step uses it when no
-    // insertion moved ahead of that entry, and loads the right row otherwise.
-    int spec_u = -1;
+    // One step expands the first unchecked entry (width 1: Algorithm 1), or the first two
+    // (width 2, R <= 32: lanes 0-31 take the first one's adjacency row, lanes 32-63 the
+    // second's).  Speculation: the rows of the entries next in line are loaded while the
+    // current step gathers and merges; the next step uses them when the same entries come
+    // up, and loads the right rows otherwise.
+    auto load_rows = [&](int x, int y) {
+        int v = -1;
+        if (a.width == 2) {
+            const int owner = lane < 32 ? x : y;
+            const int j = lane & 31;
+            if (owner >= 0 && j < a.R) v = a.adj[static_cast<int64_t>(owner) * a.R + j];
+        } else if (x >= 0 && lane < a.R) {
+            v = a.adj[static_cast<int64_t>(x) * a.R + lane];
+        }
+        return v;
+    };
+    int spec_x = -1, spec_y = -1;
     int spec_v = -1;
     while (true) {
         if (w.fill > half) {
@@ -651,51 +675,48 @@ __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_k
             w.reseed_cache();
             ++n_reset;
         }
-        // first and second unchecked entries at or after lb
-        int fu = -1, fu2 = -1;
+        // the first unchecked entries at or after lb (up to two per expanded entry; scalars,
+        // since an indexed array would live in scratch memory)
+        const int want = 2 * a.width;
+        int f0 = -1, f1 = -1, f2 = -1, f3 = -1;
+        int nf = 0;
 #pragma unroll
         for (int wi = 0; wi < CH; ++wi) {
-            if (fu2 < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
+            if (nf < want && (wi + 1) * 64 > lb && wi * 64 < w.size) {
                 const int t = wi * 64 + lane;
                 uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & kChecked));
-                if (fu < 0 && mk) {
-                    fu = wi * 64 + __builtin_ctzll(mk);
+                while (mk && nf < want) {
+                    const int pos = wi * 64 + __builtin_ctzll(mk);
+                    if (nf == 0) f0 = pos;
+                    else if (nf == 1) f1 = pos;
+                    else if (nf == 2) f2 = pos;
+                    else f3 = pos;
+                    ++nf;
                     mk &= mk - 1;
                 }
-                if (fu >= 0 && mk) fu2 = wi * 64 + __builtin_ctzll(mk);
             }
         }
-        fu = uniform(fu);
-        fu2 = uniform(fu2);
-        if (fu < 0) break;
+        if (f0 < 0) break;
         if (n_exp >= a.N) {  // unreachable for exact semantics (each node expands once)
             aborted = 1;
             break;
         }
-        uint64_t ku = 0, ku2 = 0;
-#pragma unroll
-        for (int wi = 0; wi < CH; ++wi) {
-            if (wi == (fu >> 6)) {
-                ku = readlane64(w.c[wi], fu & 63);
-                if (lane == (fu & 63)) w.c[wi] |= kChecked;
-            }
-            if (fu2 >= 0 && wi == (fu2 >> 6)) ku2 = readlane64(w.c[wi], fu2 & 63);
-        }
-        lb = fu + 1;
-        const int u = uniform(static_cast<int>(key_id(ku)));
-        ++n_exp;
+        const int nw = (a.width == 2 && f1 >= 0) ? 2 : 1;  // entries expanded now
+        auto id_at = [&](int t) { return t >= 0 ? uniform(static_cast<int>(key_id(w.key_at(t)))) : -1; };
+        const int x = id_at(f0);
+        const int y = nw == 2 ? id_at(f1) : -1;
+        const int nx = id_at(nw == 2 ? f2 : f1);
+        const int ny = (a.width == 2 && nw == 2) ? id_at(f3) : -1;
+        w.mark_checked(f0);
+        if (nw == 2) w.mark_checked(f1);
+        lb = (nw == 2 ? f1 : f0) + 1;
+        n_exp += nw;
         int v = spec_v;
-        if (u != spec_u) {
-            v = -1;
-            if (lane < a.R) v = a.adj[static_cast<int64_t>(u) * a.R + lane];
-        }
+        if (x != spec_x || y != spec_y) v = load_rows(x, y);
         if (v >= a.N) v = -1;
-        spec_u = -1;
-        spec_v = -1;
-        if (fu2 >= 0) {
-            spec_u = uniform(static_cast<int>(key_id(ku2)));
-            if (lane < a.R) spec_v = a.adj[static_cast<int64_t>(spec_u) * a.R + lane];
-        }
+        spec_x = nx;
+        spec_y = ny;
+        spec_v = nx >= 0 ? load_rows(nx, ny) : -1;
         const int mp = w.offer(v);
         lb = min(lb, mp);
     }
@@ -771,9 +792,11 @@ int beam_auto_cache_log2(int ef, int R) {
 void launch_beam(const float* Qr, int64_t m, int d_r, const void* Xr, int xr_dtype, int64_t N,
                  const int32_t* adj, int R, const int32_t* entries, int E, int ef, int metric,
                  int cache_log2, int32_t* ids, float* dists, int32_t* counters, hipStream_t s,
-                 const int32_t* efq, int visited, const int32_t* out_map, bool exact_dists) {
+                 const int32_t* efq, int visited, const int32_t* out_map, bool exact_dists, int width) {
     if (m == 0) return;
+    require(width == 1 || (width == 2 && R <= 32), "expansion width must be 1, or 2 with R <= 32");
     BeamArgs a{};
+    a.width = width;
     a.efq = efq;
     a.out_map = out_map;
     a.exact_out = exact_dists ? 1 : 0;

@@ -20,16 +20,17 @@ def say(msg):
 
 
 def traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cache_log2=0, expect_reset=False,
-                   outputs=None, bloom_log2=None):
+                   outputs=None, bloom_log2=None, width=1):
     """Stage-1 traversal of the queries qidx against the oracle.  With `outputs` = (ids,
     dists, counters) rows of an earlier launch for exactly those queries, those are checked
     instead of launching the kernel here.  bloom_log2: the Bloom-filter visited set of
-    2^bloom_log2 bits on both sides."""
+    2^bloom_log2 bits on both sides; width: entries expanded per step on both sides."""
     Qr = w["Qr32"][qidx]
     if outputs is None:
         adj = _t(w["sub_adj"].astype(np.int32), dev)
         ids, d, cnt = pa.gpu_traverse(_t(Qr, dev), Xr_dev, adj, _t(entries[qidx].astype(np.int32), dev), ef,
-                                      metric, cache_log2, bloom_log2=-1 if bloom_log2 is None else bloom_log2)
+                                      metric, cache_log2, bloom_log2=-1 if bloom_log2 is None else bloom_log2,
+                                      width=width)
         torch.cuda.synchronize()
         ids, d, cnt = ids.cpu().numpy(), d.cpu().numpy(), cnt.cpu().numpy()
     else:
@@ -41,7 +42,8 @@ def traverse_check(dev, w, Xr_host, Xr_dev, entries, ef, qidx, metric="l2", cach
     n = Xr_host.shape[0]
     for j, i in enumerate(qidx):
         ent_i = np.where((entries[i] >= 0) & (entries[i] < n), entries[i], -1)  # the kernel skips the others
-        r = oracle.greedy_search(Qr[j], Xr64, w["sr"], w["sn"], ef, ent_i, metric, bloom_log2=bloom_log2)
+        r = oracle.greedy_search(Qr[j], Xr64, w["sr"], w["sn"], ef, ent_i, metric, bloom_log2=bloom_log2,
+                                 width=width)
         k = r["ids"].size
         ref = np.full(ef, -1)
         ref[:k] = r["ids"]

@@ -196,6 +196,37 @@ def test_traverse_bloom_filter_parity(dev, tiny):
         pa.gpu_traverse(Qr, Xr, adj, _t(ent[:4].astype(np.int32), dev), 256, bloom_log2=13)
 
 
+def test_traverse_width_two_parity(dev, tiny):
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    Xr = _t(tiny["Xr32"], dev)
+    for ef, bloom, cl, nq in ((64, None, 0, 300), (16, None, 0, 200), (200, None, 0, 60), (64, 15, 0, 200),
+                              (64, None, 8, 100)):
+        say(f"gpu_traverse, two entries expanded per step: ef={ef}, Bloom 2^{bloom} bits, cache_log2={cl}")
+        _traverse_check(dev, tiny, tiny["Xr32"], Xr, ent, ef, np.arange(nq), cache_log2=cl, bloom_log2=bloom,
+                        width=2)
+    say("width 2 with fp16 rows")
+    xh = np.asarray(to_f16(tiny["Xr32"]), dtype=np.float32)
+    _traverse_check(dev, tiny, xh, _t(xh, dev, torch.float16), ent, 48, np.arange(200), width=2)
+    Qr = _t(tiny["Qr32"][:4], dev)
+    adj33 = _t(np.full((tiny["X"].shape[0], 33), -1, np.int32), dev)
+    with pytest.raises(pa.PilotannError):  # two rows of more than 32 ids do not fit one wavefront
+        pa.gpu_traverse(Qr, Xr, adj33, _t(ent[:4].astype(np.int32), dev), 16, width=2)
+    say("Index.search with width 2: recall against width 1")
+    s = tiny["spec"]
+    idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f32", r=s.r, threads=4))
+    idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+    idx.set_projection(tiny["V32"])
+    idx.build_subgraph(tiny["mask"], tiny["sr"], tiny["sn"])
+    idx.build_entries(tiny["pivots"], tiny["init"], 10)
+    gt, _ = oracle.exact_knn(tiny["X"], tiny["Q"], 10)
+    r1 = oracle.recall_at_k(idx.search(tiny["Q"], 10, 64, 64)[0], gt, 10)
+    ids2, _, cnt2, _ = idx.search(tiny["Q"], 10, 64, 64, width=2, with_counters=True)
+    r2 = oracle.recall_at_k(ids2, gt, 10)
+    say(f"  recall@10 width 1 {r1:.4f}, width 2 {r2:.4f}")
+    assert r2 >= r1 - 0.01
+    idx.close()
+
+
 def test_traverse_exact_ties_and_near_ties(dev, tiny):
     # every row repeated (equal distances: the id decides) and a copy nudged by one ulp
     # (distances a few units apart in fp32): the plain scores cannot order these, so the
@@ -304,7 +335,7 @@ def test_index_pipeline_matches_oracle(dev, tiny):
     ids_d, d_d, _, _ = idx.search(Q, 10, 64, 64, batch=300, Q_dev=Qd)
     assert (ids_d == ids).all() and (d_d.view(np.uint32) == d.view(np.uint32)).all()
     import ctypes
-    opts = pa.SearchOpts(64, 64, 0, 0, 0, 0, 0, 0, Q.ctypes.data, 0)  # a host pointer is refused
+    opts = pa.SearchOpts(64, 64, 0, 0, 0, 0, 0, 0, Q.ctypes.data, 0, 1)  # a host pointer is refused
     out_i = np.empty((Q.shape[0], 10), np.int64)
     out_d = np.empty((Q.shape[0], 10), np.float32)
     st = pa.lib().pa_search(idx._h, Q.ctypes.data_as(ctypes.c_void_p), Q.shape[0], 10, ctypes.byref(opts),
