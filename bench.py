@@ -150,19 +150,19 @@ def sweep(idx, spec, fx, target, efs):
     return (best[1], best[2]), curve
 
 
-def timed(idx, spec, fx, ef, steps, warmup, bloom=False):
+def timed(idx, spec, fx, ef, steps, warmup, bloom=False, width=1):
     import torch
     ef_gpu, ef_cpu = ef
     # the query batch is resident in HBM (for the GPU stage) and in host memory (for the
     # host stages) before the timed region; only the stage-1 hand-off crosses PCIe inside it
     Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
     for _ in range(warmup):
-        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom)
+        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom, width=width)
     torch.cuda.synchronize()
     agg = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom)
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom, width=width)
         if agg is None:
             agg = {k: 0.0 for k in st}
         for k, v in st.items():
@@ -531,7 +531,8 @@ def main():
     ap.add_argument("--no-cpu-only", action="store_true", help="skip the GPU-stage-off comparison leg")
     ap.add_argument("--no-gemm", action="store_true", help="skip the MFMA kernel leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the ablation and top-100 legs")
-    ap.add_argument("--no-bloom", action="store_true", help="skip the Bloom-filter leg of each form")
+    ap.add_argument("--no-bloom", action="store_true",
+                    help="skip the stage-1 variant legs (Bloom filter, expansion width 2) of each form")
     ap.add_argument("--ratio-sweep", action="store_true", help="add the (rho, d_r) grid (nine index builds)")
     ap.add_argument("--forms", default="f32,f16")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
@@ -589,16 +590,21 @@ def main():
             "curve": curve,
         }
         log(f"{form}: ef={ef} recall={rec:.4f} qps={qps:,.0f} roofline={forms[form]['roofline']}")
-        if not args.no_bloom:
-            dtb, aggb, recb = timed(idx, spec, fx, ef, args.steps, args.warmup, bloom=True)
-            forms[form]["bloom"] = {
-                "what": "stage 1 with the Bloom-filter visited set of section 4.3 (automatic size, 32 bits per "
-                        "cache slot) instead of the exact cache, same ef",
-                "value": round(spec.queries * args.steps / dtb, 1), "recall": round(recb, 5),
-                "ms_per_step": round(dtb * 1e3 / args.steps, 3),
-                "roofline": roofline(spec, aggb, args.steps, ef[0], E, xr_bytes, form + "+bloom"),
-                "mean_n_dist1": round(aggb["n_dist1"] / (spec.queries * args.steps), 1)}
-            log(f"{form} with the Bloom filter: recall={recb:.4f} roofline={forms[form]['bloom']['roofline']}")
+        if not args.no_bloom:  # stage-1 variants at the same ef
+            variants = {"bloom": ("the Bloom-filter visited set of section 4.3 (automatic size, 32 bits per "
+                                  "cache slot) instead of the exact cache", True, 1),
+                        "width2": ("two unchecked entries expanded per step (not the paper's Algorithm 1)", False, 2),
+                        "bloom+width2": ("both", True, 2)}
+            forms[form]["variants"] = {}
+            for name, (what, bloom, width) in variants.items():
+                dtb, aggb, recb = timed(idx, spec, fx, ef, args.steps, args.warmup, bloom=bloom, width=width)
+                forms[form]["variants"][name] = {
+                    "what": what, "value": round(spec.queries * args.steps / dtb, 1), "recall": round(recb, 5),
+                    "ms_per_step": round(dtb * 1e3 / args.steps, 3),
+                    "roofline": roofline(spec, aggb, args.steps, ef[0], E, xr_bytes, f"{form}+{name}"),
+                    "mean_n_exp1": round(aggb["n_exp1"] / (spec.queries * args.steps), 1),
+                    "mean_n_dist1": round(aggb["n_dist1"] / (spec.queries * args.steps), 1)}
+                log(f"{form} {name}: recall={recb:.4f} roofline={forms[form]['variants'][name]['roofline']}")
         if form == "f32" and not args.no_cpu_only:
             log("cpu-only (GPU stage off)")
             baseline_cpu_only = cpu_only(idx, spec, fx, args.target, max(1, min(args.steps, 3)))
