@@ -625,7 +625,7 @@ struct Wave {
 // One-register lists fit in 72 VGPRs, which allows 7 waves per SIMD (LDS allows about as
 // many), two-register lists in 80 (6 waves); only the variants with a run-time lane count
 // spill a few values.  Larger lists keep the compiler's choice.
-template <int DT, int MET, int CH, int GSL>
+template <int DT, int MET, int CH, int GSL, int WIDTH>
 __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_kernel(BeamArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_k
     // up, and loads the right rows otherwise.
     auto load_rows = [&](int x, int y) {
         int v = -1;
-        if (a.width == 2) {
+        if (WIDTH == 2) {
             const int owner = lane < 32 ? x : y;
             const int j = lane & 31;
             if (owner >= 0 && j < a.R) v = a.adj[static_cast<int64_t>(owner) * a.R + j];
@@ -675,38 +675,60 @@ __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_k
             w.reseed_cache();
             ++n_reset;
         }
-        // the first unchecked entries at or after lb (up to two per expanded entry; scalars,
-        // since an indexed array would live in scratch memory)
-        const int want = 2 * a.width;
+        // the first unchecked entries at or after lb: two for width 1 (the one expanded and
+        // the next in line), four for width 2 (scalars: an indexed array would live in
+        // scratch memory)
         int f0 = -1, f1 = -1, f2 = -1, f3 = -1;
-        int nf = 0;
+        if (WIDTH == 1) {
 #pragma unroll
-        for (int wi = 0; wi < CH; ++wi) {
-            if (nf < want && (wi + 1) * 64 > lb && wi * 64 < w.size) {
-                const int t = wi * 64 + lane;
-                uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & kChecked));
-                while (mk && nf < want) {
-                    const int pos = wi * 64 + __builtin_ctzll(mk);
-                    if (nf == 0) f0 = pos;
-                    else if (nf == 1) f1 = pos;
-                    else if (nf == 2) f2 = pos;
-                    else f3 = pos;
-                    ++nf;
-                    mk &= mk - 1;
+            for (int wi = 0; wi < CH; ++wi) {
+                if (f1 < 0 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
+                    const int t = wi * 64 + lane;
+                    uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & kChecked));
+                    if (f0 < 0 && mk) {
+                        f0 = wi * 64 + __builtin_ctzll(mk);
+                        mk &= mk - 1;
+                    }
+                    if (f0 >= 0 && mk) f1 = wi * 64 + __builtin_ctzll(mk);
+                }
+            }
+        } else {
+            int nf = 0;
+#pragma unroll
+            for (int wi = 0; wi < CH; ++wi) {
+                if (nf < 4 && (wi + 1) * 64 > lb && wi * 64 < w.size) {
+                    const int t = wi * 64 + lane;
+                    uint64_t mk = __ballot(t >= lb && t < w.size && !(w.c[wi] & kChecked));
+                    while (mk && nf < 4) {
+                        const int pos = wi * 64 + __builtin_ctzll(mk);
+                        if (nf == 0) f0 = pos;
+                        else if (nf == 1) f1 = pos;
+                        else if (nf == 2) f2 = pos;
+                        else f3 = pos;
+                        ++nf;
+                        mk &= mk - 1;
+                    }
                 }
             }
         }
+        f0 = uniform(f0);
+        f1 = uniform(f1);
         if (f0 < 0) break;
         if (n_exp >= a.N) {  // unreachable for exact semantics (each node expands once)
             aborted = 1;
             break;
         }
-        const int nw = (a.width == 2 && f1 >= 0) ? 2 : 1;  // entries expanded now
+        const int nw = (WIDTH == 2 && f1 >= 0) ? 2 : 1;  // entries expanded now
         auto id_at = [&](int t) { return t >= 0 ? uniform(static_cast<int>(key_id(w.key_at(t)))) : -1; };
         const int x = id_at(f0);
-        const int y = nw == 2 ? id_at(f1) : -1;
-        const int nx = id_at(nw == 2 ? f2 : f1);
-        const int ny = (a.width == 2 && nw == 2) ? id_at(f3) : -1;
+        int y = -1, nx, ny = -1;
+        if (nw == 2) {
+            y = id_at(f1);
+            nx = id_at(f2);
+            ny = id_at(f3);
+        } else {
+            nx = id_at(f1);
+        }
         w.mark_checked(f0);
         if (nw == 2) w.mark_checked(f1);
         lb = (nw == 2 ? f1 : f0) + 1;
@@ -748,13 +770,20 @@ __global__ __launch_bounds__(256, (CH == 1 ? 7 : (CH == 2 ? 6 : 1))) void beam_k
     }
 }
 
-template <int DT, int MET, int CH, int GSL>
-void launch_typed(BeamArgs a, hipStream_t s) {
+template <int DT, int MET, int CH, int GSL, int WIDTH>
+void launch_wide(BeamArgs a, hipStream_t s) {
     a.wave_bytes = wave_lds_bytes<CH>(a.hlog);
     const int wpb = a.wave_bytes * 2 <= 64 * 1024 ? 2 : 1;
     const int blocks = static_cast<int>((a.m + wpb - 1) / wpb);
     const size_t lds = static_cast<size_t>(a.wave_bytes) * wpb;
-    hipLaunchKernelGGL((beam_kernel<DT, MET, CH, GSL>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((beam_kernel<DT, MET, CH, GSL, WIDTH>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+}
+
+// width 1 (Algorithm 1) and width 2 get separate code, so that width 1 pays nothing for 2
+template <int DT, int MET, int CH, int GSL>
+void launch_typed(const BeamArgs& a, hipStream_t s) {
+    if (a.width == 2) launch_wide<DT, MET, CH, GSL, 2>(a, s);
+    else launch_wide<DT, MET, CH, GSL, 1>(a, s);
 }
 
 // 4 and 8 lanes per vector (reduced rows of 64 to 128 fp32 or 128 to 256 16-bit elements)
