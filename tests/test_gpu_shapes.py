@@ -144,3 +144,23 @@ def test_l2_96_fp16_traversal_and_index(dev, l2_96):
         tally.check(d[i], oracle.as_f32(oracle.delta_many(w["Q"][i], w["X"][ids[i]])), i)
     tally.done()
     idx.close()
+
+
+def test_ip768_compact_layout_matches_full(dev, ip768):
+    say("Index: 768-d IP, bf16 X_r, fp8 pivots; compact layout against the full layout, and a checkpoint round trip")
+    w = ip768
+    s = w["spec"]
+    out = []
+    for compact in (False, True):
+        idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric="ip", xr_dtype="bf16", r=s.r, threads=4,
+                                      pivot_dtype="fp8", compact=compact))
+        idx.set_data(w["X"], w["rp"], w["nb"])
+        idx.set_projection(w["V32"])
+        idx.build_subgraph(w["mask"], w["sr"], w["sn"])
+        idx.build_entries(w["pivots"], w["init"], 10)
+        ids, d, _, _ = idx.search(w["Q"], 10, 128, 128)
+        out.append((ids, d, idx.info()))
+        idx.close()
+    (i0, d0, f0), (i1, d1, f1) = out
+    assert (i0 == i1).all() and (d0.view(np.uint32) == d1.view(np.uint32)).all()
+    assert f1["xr_rows"] == int(w["mask"].sum()) and f1["hbm_bytes"] < f0["hbm_bytes"]
