@@ -242,3 +242,28 @@ def test_fp8_row_encoding_matches_torch_e4m3fn():
     # the largest magnitude of every non-zero row encodes to +-448
     nz = amax > 0
     assert (np.abs(torch.tensor(codes).view(torch.float8_e4m3fn).float().numpy()).max(1)[nz] == 448).all()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library every call raises: the binding has no fallback of its own."""
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, paper_2503_21206_amd as pa\n"
+        f"pa.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "pa._lib = None\n"
+        "for call in (lambda: pa.abi_version(),\n"
+        "             lambda: pa.sample_nodes(np.zeros(2, np.int64), np.zeros(0, np.int32), np.zeros(1, np.int64), 1),\n"
+        "             lambda: pa.cpu_search(np.zeros((4, 8), np.float32), np.full((4, 2), -1, np.int32),\n"
+        "                                   np.zeros((1, 8), np.float32), np.zeros((1, 1), np.int32), 4, 1)):\n"
+        "    try:\n"
+        "        call()\n"
+        "    except RuntimeError as e:\n"
+        "        assert 'missing' in str(e), e\n"
+        "    else:\n"
+        "        raise SystemExit('a call returned without the library')\n"
+        "print('ok')\n"
+    )
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
