@@ -344,8 +344,10 @@ def roofline(spec, agg, steps, ef, E, xr_bytes, form):
 
 def memory_leg(spec, fx, shared, ef, full_info, steps):
     """Memory-bounded layout (X_r and the device subgraph for the sampled nodes only, fp16
-    rows) at several sampling ratios: HBM held by the index, QPS and recall at ef."""
+    rows) at several sampling ratios: HBM held by the index (and the library's model of
+    it), QPS and recall at ef; then the (rho, d_r) the planner picks for a few budgets."""
     import dataclasses
+    import paper_2503_21206_amd as pa
     out = {"what": "compact layout, fp16 X_r, ef_gpu/ef_cpu as timed; hbm_bytes = index tables and search "
                    "buffers on the device",
            "full_layout_rho_0.25": {"hbm_bytes": full_info["hbm_bytes"], "xr_rows": full_info["xr_rows"]},
@@ -356,11 +358,29 @@ def memory_leg(spec, fx, shared, ef, full_info, steps):
         idx = build_index(sp, fx, "f16", sh, compact=True)
         dt, agg, rec = timed(idx, sp, fx, ef, steps, 1)
         info = idx.info()
-        out["points"].append({"rho": rho, "hbm_bytes": info["hbm_bytes"], "xr_rows": info["xr_rows"],
+        # the library's HBM model for the same shape (the timed searches pass q_dev)
+        shape = pa.memory_shape(sp.n, sp.dim, info["R_sub"], sp.n_pivots, sp.r, "f16", queries=sp.queries,
+                                ef_gpu=ef[0], q_on_device=True)
+        out["points"].append({"rho": rho, "hbm_bytes": info["hbm_bytes"],
+                              "model_hbm_bytes": pa.hbm_bytes(shape, info["xr_rows"] / sp.n, sp.d_r),
+                              "xr_rows": info["xr_rows"],
                               "qps": round(sp.queries * steps / dt, 1), "recall": round(rec, 5),
                               "mean_n_dist3": round(agg["n_dist3"] / (sp.queries * steps), 1)})
         log(f"  compact rho={rho}: {out['points'][-1]}")
         idx.close()
+    # the planner's choice per HBM budget over the (rho, d_r) grid, at the reconnection
+    # degree cap (the subgraph's padded degree is at most that)
+    shape = pa.memory_shape(spec.n, spec.dim, spec.degree, spec.n_pivots, spec.r, "f16", queries=spec.queries,
+                            ef_gpu=ef[0], q_on_device=True)
+    rhos, widths = [0.1, 0.25, 0.5, 0.75, 1.0], [32, 64, 128]
+    out["plan"] = {"rhos": rhos, "d_r": widths, "choices": []}
+    for mb in (32, 64, 128, 256):
+        try:
+            rho, d_r, b = pa.plan_memory(shape, mb << 20, rhos, widths)
+            out["plan"]["choices"].append({"budget_mib": mb, "rho": rho, "d_r": d_r, "hbm_bytes": b})
+        except pa.PilotannError:
+            out["plan"]["choices"].append({"budget_mib": mb, "rho": None})
+    log(f"  plan: {out['plan']['choices']}")
     return out
 
 

@@ -394,6 +394,54 @@ typedef struct {
 
 pa_status pa_index_get_info(const pa_index* idx, pa_index_info* out);
 
+/* ----------------------------------------------------- memory-bounded mode */
+
+/* The HBM an index and its searches hold, as a function of the sampling ratio and the
+ * reduced width: the paper fits the subgraph and the reduced vectors to the GPU's memory
+ * (section 6.2, minimum GPU memory study; the sampling and SVD ratios of Table 3). */
+typedef struct {
+    int64_t N;            /* base vectors                                               */
+    int32_t dim;          /* D                                                          */
+    int32_t xr_dtype;     /* PA_F32 / PA_F16 / PA_BF16                                  */
+    int32_t pivot_dtype;  /* PA_F32 / PA_FP8E4M3                                        */
+    int32_t compact;      /* layout, as pa_params.compact                               */
+    int32_t R_sub;        /* padded subgraph degree (1..1024)                           */
+    int32_t n_pivots;     /* FES pivots, a multiple of r                                */
+    int32_t r;            /* FES buckets                                                */
+    int64_t queries;      /* queries of the largest pa_search call (0: none yet)        */
+    int32_t batch;        /* pa_search_opts.batch (0: 16,384)                           */
+    int32_t ef_gpu;       /* pa_search_opts.ef_gpu (1..PA_MAX_EF)                       */
+    int32_t E;            /* pa_search_opts.E (0: min(ef_gpu, n_pivots / r))            */
+    int32_t q_on_device;  /* 1: the searches pass their queries as q_dev                */
+} pa_memory_shape;
+
+/* Device bytes that an index of this shape holds once built with n_s = round(rho * N)
+ * sampled nodes and reduced width d_r and after searches of up to `queries` queries: the
+ * value pa_index_get_info then reports as hbm_bytes.  With s = 4, 2, 2 bytes per element
+ * for F32, F16, BF16, n = n_s in the compact layout and N otherwise, m = queries and B =
+ * min(m, batch) (the largest sub-batch), it is the sum of
+ *   4*D*d_r                                       projection
+ *   max(16, n*d_r*s) + 4*max(n, 1)*R_sub           X_r and the device subgraph
+ *   4*max(n_s, 1)                                 device-to-node ids (compact layout)
+ *   4*n_p*(d_r + 2) + 4*r*d_r                     pivot rows, norms and ids; centroids
+ *   n_p*(d_r + 4)                                 FP8 pivot codes and scales (FP8 form)
+ *   m*(4*D + 4*d_r + 4 + 8*E + 8*ef_gpu + 16) + 4*(3*r + 2 + B)   search buffers (m > 0;
+ *                                                 the 4*D term only without q_on_device)
+ * Returns -1 for an invalid shape, rho outside (0, 1] or d_r outside 16..D or not a
+ * multiple of 16. */
+int64_t pa_hbm_bytes(const pa_memory_shape* shape, double rho, int32_t d_r);
+
+/* Memory-bounded mode: from the candidate ratios rhos[n_rho] and widths d_rs[n_dr],
+ * choose the pair whose pa_hbm_bytes fits hbm_budget with the largest rho (a larger
+ * sample holds more of each query's answers for stage 1), and at that rho the largest
+ * d_r.  Writes the pair and its bytes (any output may be NULL).  PA_EHBM when no pair
+ * fits; PA_EINVAL for an invalid shape or candidate, or an empty candidate list.  An
+ * index built with the chosen pair and hbm_budget as pa_params.hbm_budget then holds
+ * exactly the predicted bytes. */
+pa_status pa_plan_memory(const pa_memory_shape* shape, int64_t hbm_budget, const double* rhos, int32_t n_rho,
+                         const int32_t* d_rs, int32_t n_dr, double* rho_out, int32_t* d_r_out,
+                         int64_t* bytes_out);
+
 /* Device pointers of the index's tables (for stage-isolated calls); any may be NULL.
  * In the compact layout X_r, the adjacency and EVid hold device ids (see
  * pa_index_build_subgraph). */

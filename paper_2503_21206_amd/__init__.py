@@ -72,6 +72,13 @@ class ServerParams(C.Structure):
                 ("threads", C.c_int32), ("max_k", C.c_int32)]
 
 
+class MemoryShape(C.Structure):
+    _fields_ = [("N", C.c_int64), ("dim", C.c_int32), ("xr_dtype", C.c_int32), ("pivot_dtype", C.c_int32),
+                ("compact", C.c_int32), ("R_sub", C.c_int32), ("n_pivots", C.c_int32), ("r", C.c_int32),
+                ("queries", C.c_int64), ("batch", C.c_int32), ("ef_gpu", C.c_int32), ("E", C.c_int32),
+                ("q_on_device", C.c_int32)]
+
+
 class ResultInfo(C.Structure):
     _fields_ = [("tag", C.c_uint64), ("k", C.c_int32), ("ef", C.c_int32), ("t_submit_us", C.c_double),
                 ("t_admit_us", C.c_double), ("t_done_us", C.c_double)]
@@ -125,7 +132,11 @@ _SIGS = {
     "pa_server_drain": [_P],
     "pa_server_stats": [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64)],
     "pa_server_destroy": [_P],
+    "pa_hbm_bytes": [C.POINTER(MemoryShape), _F64, _I32],
+    "pa_plan_memory": [C.POINTER(MemoryShape), _I64, _P, _I32, _P, _I32, C.POINTER(_F64), C.POINTER(_I32),
+                       C.POINTER(_I64)],
 }
+_RESTYPES = {"pa_hbm_bytes": C.c_int64}  # the others return an int32 status
 
 _lib = None
 
@@ -142,7 +153,7 @@ def lib():
         for name, args in _SIGS.items():
             fn = getattr(h, name)
             fn.argtypes = args
-            fn.restype = C.c_int32
+            fn.restype = _RESTYPES.get(name, C.c_int32)
         _lib = h
     return _lib
 
@@ -433,6 +444,33 @@ def cpu_search(X, full_adj, Q, entries, ef: int, k: int, metric: str = "l2", thr
 
 
 # ------------------------------------------------------------------ index
+
+def memory_shape(N: int, dim: int, R_sub: int, n_pivots: int, r: int = 32, xr_dtype: str = "f16",
+                 pivot_dtype: str = "f32", compact: bool = True, queries: int = 0, batch: int = 0, ef_gpu: int = 64,
+                 E: int = 0, q_on_device: bool = False) -> MemoryShape:
+    """The shape pa_hbm_bytes and pa_plan_memory take (fields as in include/pilotann.h)."""
+    return MemoryShape(N, dim, DTYPES[xr_dtype], {"f32": PA_F32, "fp8": PA_FP8E4M3}[pivot_dtype],
+                       1 if compact else 0, R_sub, n_pivots, r, queries, batch, ef_gpu, E, 1 if q_on_device else 0)
+
+
+def hbm_bytes(shape: MemoryShape, rho: float, d_r: int) -> int:
+    """Device bytes an index of this shape holds at sampling ratio rho and width d_r."""
+    b = lib().pa_hbm_bytes(C.byref(shape), float(rho), int(d_r))
+    if b < 0:
+        raise PilotannError(-1, f"invalid memory shape, ratio {rho} or width {d_r}")
+    return int(b)
+
+
+def plan_memory(shape: MemoryShape, hbm_budget: int, rhos, d_rs):
+    """(rho, d_r, bytes): the candidate pair that fits hbm_budget with the largest rho, then
+    the largest d_r (memory-bounded mode)."""
+    rh = np.ascontiguousarray(rhos, dtype=np.float64)
+    dr = np.ascontiguousarray(d_rs, dtype=np.int32)
+    rho, d, b = C.c_double(), C.c_int32(), C.c_int64()
+    _check(lib().pa_plan_memory(C.byref(shape), int(hbm_budget), rh.ctypes.data_as(_P), rh.size,
+                                dr.ctypes.data_as(_P), dr.size, C.byref(rho), C.byref(d), C.byref(b)))
+    return rho.value, d.value, b.value
+
 
 @dataclass
 class IndexConfig:

@@ -291,7 +291,7 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pa_abi_version(void) { return 8; }
+int32_t pa_abi_version(void) { return 9; }
 
 pa_status pa_device_init(int32_t device) {
     return guarded([&] {

@@ -142,6 +142,38 @@ void index_upload_subgraph(pa_index* idx) {
     if (n > 0) PA_HIP(hipMemcpy(idx->cid_dev.p, idx->cid.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
 }
 
+// The model follows the ensure() calls of this file term by term: project_all (V),
+// index_write_rows (X_r), index_upload_subgraph (adjacency, id map), build_entries (pivot
+// table, centroids, FP8 codes) and search (its grow-only buffers).
+int64_t index_hbm_model(const pa_memory_shape& s, double rho, int d_r) {
+    const bool dtype_ok = s.xr_dtype == PA_F32 || s.xr_dtype == PA_F16 || s.xr_dtype == PA_BF16;
+    if (s.N <= 0 || s.dim <= 0 || !dtype_ok || (s.pivot_dtype != PA_F32 && s.pivot_dtype != PA_FP8E4M3) ||
+        s.R_sub < 1 || s.R_sub > 1024 || s.r < 1 || s.n_pivots < s.r || s.n_pivots % s.r != 0 || s.queries < 0 ||
+        s.batch < 0 || s.ef_gpu < 1 || s.ef_gpu > PA_MAX_EF || s.E < 0 || s.E > PA_MAX_EF)
+        return -1;
+    if (!(rho > 0.0 && rho <= 1.0) || d_r < 16 || d_r > s.dim || d_r % 16 != 0) return -1;
+    const int64_t D = s.dim, dr = d_r, np = s.n_pivots, r = s.r, R = s.R_sub;
+    const int64_t es = static_cast<int64_t>(dtype_size(s.xr_dtype));
+    const int64_t ns = std::llround(rho * static_cast<double>(s.N));
+    const int64_t n = s.compact ? ns : s.N;
+    int64_t b = 4 * D * dr;                                  // V
+    b += std::max<int64_t>(16, n * dr * es);                 // X_r
+    b += 4 * std::max<int64_t>(n, 1) * R;                    // device adjacency
+    if (s.compact) b += 4 * std::max<int64_t>(ns, 1);        // device-to-node ids
+    b += 4 * np * dr + 4 * np + 4 * np + 4 * r * dr;         // EV, EVnorm, EVid, centroids
+    if (s.pivot_dtype == PA_FP8E4M3) b += np * dr + 4 * np;  // e4m3 codes, row scales
+    if (s.queries > 0) {
+        const int64_t m = s.queries;
+        const int64_t E = s.E > 0 ? s.E : std::min<int64_t>(s.ef_gpu, np / r);
+        const int64_t B = std::min<int64_t>(m, s.batch > 0 ? s.batch : 16384);
+        if (!s.q_on_device) b += 4 * m * D;                  // queries
+        b += 4 * m * dr + 4 * m;                             // reduced queries, buckets
+        b += 8 * m * E + 8 * m * s.ef_gpu + 16 * m;          // entries, stage-1 lists, counters
+        b += 4 * static_cast<int64_t>(select_entries_scratch_ints(B, s.r));
+    }
+    return b;
+}
+
 namespace {
 
 double elapsed_ms(hipEvent_t a, hipEvent_t b) {
@@ -530,6 +562,39 @@ pa_status pa_index_device_tables(const pa_index* idx, const void** Xr_dev, const
         if (EV_dev) *EV_dev = static_cast<const float*>(idx->EV_dev.p);
         if (EVnorm_dev) *EVnorm_dev = static_cast<const float*>(idx->EVn_dev.p);
         if (EVid_dev) *EVid_dev = static_cast<const int32_t*>(idx->EVid_dev.p);
+    });
+}
+
+int64_t pa_hbm_bytes(const pa_memory_shape* shape, double rho, int32_t d_r) {
+    if (shape == nullptr) return -1;
+    return index_hbm_model(*shape, rho, d_r);
+}
+
+pa_status pa_plan_memory(const pa_memory_shape* shape, int64_t hbm_budget, const double* rhos, int32_t n_rho,
+                         const int32_t* d_rs, int32_t n_dr, double* rho_out, int32_t* d_r_out, int64_t* bytes_out) {
+    return guarded([&] {
+        require(shape && rhos && d_rs, "null pointer");
+        require(n_rho >= 1 && n_dr >= 1, "need at least one candidate ratio and width");
+        require(hbm_budget > 0, "hbm_budget must be positive");
+        double best_rho = -1.0;
+        int best_dr = -1;
+        int64_t best_bytes = -1;
+        for (int i = 0; i < n_rho; ++i)
+            for (int j = 0; j < n_dr; ++j) {
+                const int64_t b = index_hbm_model(*shape, rhos[i], d_rs[j]);
+                require(b >= 0, "invalid shape, ratio " + std::to_string(rhos[i]) + " or width " +
+                                    std::to_string(d_rs[j]));
+                if (b > hbm_budget) continue;
+                if (rhos[i] > best_rho || (rhos[i] == best_rho && d_rs[j] > best_dr)) {
+                    best_rho = rhos[i];
+                    best_dr = d_rs[j];
+                    best_bytes = b;
+                }
+            }
+        require(best_dr > 0, "no candidate fits " + std::to_string(hbm_budget) + " bytes of HBM", PA_EHBM);
+        if (rho_out) *rho_out = best_rho;
+        if (d_r_out) *d_r_out = best_dr;
+        if (bytes_out) *bytes_out = best_bytes;
     });
 }
 

@@ -100,6 +100,8 @@ inline const int32_t* index_out_map(const pa_index* idx) {
 int32_t index_device_id(const pa_index* idx, int32_t node);  // -1 if not held on the device
 // (Re)writes X_r (all rows, or the sampled rows of the compact layout) from X and V.
 void index_write_rows(pa_index* idx);
+// Device bytes an index of shape s holds (pa_hbm_bytes); -1 if the shape is invalid.
+int64_t index_hbm_model(const pa_memory_shape& s, double rho, int d_r);
 // Uploads the device adjacency (and the id map of the compact layout) from sub_adj.
 void index_upload_subgraph(pa_index* idx);
 // Entry selection for m reduced queries with the index's tables (fp32 or FP8 form).

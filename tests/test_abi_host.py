@@ -26,7 +26,7 @@ def _declared():
     for f in os.listdir(os.path.join(ROOT, "include")):
         if f.endswith(".h"):
             text = open(os.path.join(ROOT, "include", f)).read()
-            names |= set(re.findall(r"^\s*(?:pa_status|const char\*|int32_t)\s+(pa_[a-z0-9_]+)\s*\(", text, re.M))
+            names |= set(re.findall(r"^\s*(?:pa_status|const char\*|int32_t|int64_t)\s+(pa_[a-z0-9_]+)\s*\(", text, re.M))
     return names
 
 
@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
     for name in decl:
         assert hasattr(L, name), name
     assert decl == set(pa.symbols())
-    assert pa.abi_version() == 8
+    assert pa.abi_version() == 9
 
 
 def _csr(rows):
@@ -267,3 +267,37 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
                        cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
+
+
+def test_hbm_model_hand_sums_and_planner_choice():
+    """The device-byte model of the memory-bounded mode, worked by hand on a small shape,
+    and the planner's rule (largest ratio that fits, then the largest width)."""
+    shape = pa.memory_shape(N=1000, dim=32, R_sub=8, n_pivots=64, r=4, xr_dtype="f16")
+    # rho 0.25 -> 250 sampled rows, d_r 16, 2-byte rows: V 4*32*16 = 2048, X_r 250*16*2 = 8000,
+    # adjacency 4*250*8 = 8000, id map 4*250 = 1000, pivots 4*64*(16+2) = 4608, centroids
+    # 4*4*16 = 256
+    assert pa.hbm_bytes(shape, 0.25, 16) == 2048 + 8000 + 8000 + 1000 + 4608 + 256
+    full = pa.memory_shape(N=1000, dim=32, R_sub=8, n_pivots=64, r=4, xr_dtype="f16", compact=False)
+    assert pa.hbm_bytes(full, 0.25, 16) == 2048 + 32000 + 32000 + 4608 + 256  # every row, no id map
+    fp8 = pa.memory_shape(N=1000, dim=32, R_sub=8, n_pivots=64, r=4, xr_dtype="f16", pivot_dtype="fp8")
+    assert pa.hbm_bytes(fp8, 0.25, 16) == 23912 + 64 * (16 + 4)
+    # 10 queries, ef 8, E = min(8, 64/4): 10*(4*32 + 4*16 + 4 + 8*8 + 8*8 + 16) + 4*(3*4 + 2 + 10)
+    q = pa.memory_shape(N=1000, dim=32, R_sub=8, n_pivots=64, r=4, xr_dtype="f16", queries=10, ef_gpu=8)
+    assert pa.hbm_bytes(q, 0.25, 16) == 23912 + 3400 + 96
+    qd = pa.memory_shape(N=1000, dim=32, R_sub=8, n_pivots=64, r=4, xr_dtype="f16", queries=10, ef_gpu=8,
+                         q_on_device=True)
+    assert pa.hbm_bytes(qd, 0.25, 16) == 23912 + 3400 + 96 - 10 * 4 * 32
+    rhos, widths = [0.1, 0.25, 0.5], [16, 32]
+    cost = {(r_, d_): pa.hbm_bytes(shape, r_, d_) for r_ in rhos for d_ in widths}
+    assert cost[(0.5, 16)] < cost[(0.5, 32)] and cost[(0.25, 32)] < cost[(0.5, 16)]
+    # a budget between (0.25, 32) and (0.5, 16): the largest ratio that fits is 0.25, at its widest
+    assert pa.plan_memory(shape, cost[(0.5, 16)] - 1, rhos, widths) == (0.25, 32, cost[(0.25, 32)])
+    assert pa.plan_memory(shape, cost[(0.5, 16)], rhos, widths) == (0.5, 16, cost[(0.5, 16)])
+    assert pa.plan_memory(shape, 10 ** 12, rhos, widths) == (0.5, 32, cost[(0.5, 32)])
+    with pytest.raises(pa.PilotannError) as e:
+        pa.plan_memory(shape, cost[(0.1, 16)] - 1, rhos, widths)
+    assert e.value.status == -4  # PA_EHBM: nothing fits
+    for bad_rho, bad_w in ((0.0, 16), (1.5, 16), (0.25, 24), (0.25, 48)):
+        with pytest.raises(pa.PilotannError) as e:
+            pa.plan_memory(shape, 10 ** 12, [bad_rho], [bad_w])
+        assert e.value.status == -1

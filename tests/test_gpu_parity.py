@@ -416,6 +416,49 @@ def test_compact_layout_matches_full_layout(dev, tiny, tmp_path):
     assert abs(rb_full - rb_comp) <= 0.01
 
 
+def test_memory_model_predicts_the_index_bytes(dev, tiny):
+    say("memory-bounded mode: the HBM model against the bytes three index forms hold, and the planner's budget")
+    s = tiny["spec"]
+    Q = tiny["Q"]
+    N = tiny["X"].shape[0]
+    rho = int(tiny["mask"].sum()) / N
+    n_p = len(tiny["pivots"])
+
+    def build(compact, xr, piv, budget=0):
+        idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype=xr, r=s.r, threads=4,
+                                      compact=compact, pivot_dtype=piv, hbm_budget=budget))
+        idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+        idx.set_projection(tiny["V32"])
+        idx.build_subgraph(tiny["mask"], tiny["sr"], tiny["sn"])
+        idx.build_entries(tiny["pivots"], tiny["init"], 10)
+        return idx
+
+    for compact, xr, piv in ((True, "f16", "f32"), (False, "f32", "f32"), (True, "bf16", "fp8")):
+        idx = build(compact, xr, piv)
+        R_sub = idx.info()["R_sub"]
+        shape = pa.memory_shape(N, s.dim, R_sub, n_p, s.r, xr, piv, compact)
+        assert idx.info()["hbm_bytes"] == pa.hbm_bytes(shape, rho, s.d_r), (compact, xr, piv)
+        idx.search(Q, 10, 64, 64, batch=300)
+        shape = pa.memory_shape(N, s.dim, R_sub, n_p, s.r, xr, piv, compact, queries=Q.shape[0], batch=300,
+                                ef_gpu=64)
+        assert idx.info()["hbm_bytes"] == pa.hbm_bytes(shape, rho, s.d_r), (compact, xr, piv)
+        idx.close()
+    # the planner's pair for a budget of exactly its bytes: the index builds and searches
+    # within it, and one byte less is refused when the search buffers are allocated
+    shape = pa.memory_shape(N, s.dim, R_sub, n_p, s.r, "f16", queries=Q.shape[0], batch=300, ef_gpu=64)
+    need = pa.hbm_bytes(shape, rho, s.d_r)
+    assert pa.plan_memory(shape, need, [rho], [16, s.d_r, 2 * s.d_r]) == (rho, s.d_r, need)
+    idx = build(True, "f16", "f32", budget=need)
+    ids, _, _, _ = idx.search(Q, 10, 64, 64, batch=300)
+    assert idx.info()["hbm_bytes"] == need and (ids >= 0).all()
+    idx.close()
+    idx = build(True, "f16", "f32", budget=need - 1)
+    with pytest.raises(pa.PilotannError) as e:
+        idx.search(Q, 10, 64, 64, batch=300)
+    assert e.value.status == -4  # PA_EHBM
+    idx.close()
+
+
 def test_gpu_only_special_case(dev, tiny):
     say("GPU-only special case: every node sampled, d_r = D, no final traversal; against the oracle")
     s = tiny["spec"]
