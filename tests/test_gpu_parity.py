@@ -139,6 +139,41 @@ def test_select_entries(dev, tiny):
     _fes_check(dev, tiny, 3, tiny["Qr32"][:5])
 
 
+def test_route_and_entries_with_64_buckets(dev, tiny):
+    say("r = 64 buckets (one per lane of a wavefront): routing, select_entries E=4, and the index build")
+    from synth import kmeans_init_choice
+    s = tiny["spec"]
+    r = 64
+    init = kmeans_init_choice(s.n_pivots, r, s.seed)
+    b, cent = oracle.balanced_kmeans(tiny["P32"], r, init)
+    w = dict(tiny, buckets=b, cent32=cent.astype(np.float32))
+    Q, V = tiny["Q"], tiny["V32"]
+    _, cl = pa.project_route(_t(Q, dev), _t(V, dev), _t(w["cent32"], dev))
+    cl = cl.cpu().numpy()
+    Qr64 = Q.astype(np.float64) @ V.astype(np.float64)
+    bad = 0
+    for i in range(Q.shape[0]):
+        c, margin = oracle.route(Qr64[i], cent)
+        if c != cl[i]:
+            assert margin < 1e-4, (i, c, cl[i], margin)
+            bad += 1
+    assert bad <= Q.shape[0] // 1000
+    assert _fes_check(dev, w, 4, tiny["Qr32"]) <= Q.shape[0] // 1000
+    # the index clusters its pivots into the same 64 buckets and searches with them
+    idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, r=r, threads=4))
+    idx.set_data(tiny["X"], tiny["rp"], tiny["nb"])
+    idx.set_projection(V)
+    idx.build_subgraph(tiny["mask"], tiny["sr"], tiny["sn"])
+    idx.build_entries(tiny["pivots"], init, 10)
+    _, buckets, _ = idx.state()  # balanced: 64 buckets of 4, every pivot once
+    assert buckets.shape == (r, s.n_pivots // r) and np.array_equal(np.sort(buckets.ravel()), np.sort(tiny["pivots"]))
+    ids, d, _, _ = idx.search(Q, 10, 64, 64)
+    rec = oracle.recall_at_k(ids, oracle.exact_knn(tiny["X"], Q, 10)[0], 10)
+    say(f"  recall@10 {rec:.4f}")
+    assert rec >= 0.9
+    idx.close()
+
+
 # ------------------------------------------------------------ traversal
 
 def test_traverse_f32_parity(dev, tiny):
