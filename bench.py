@@ -384,6 +384,38 @@ def memory_leg(spec, fx, shared, ef, full_info, steps):
     return out
 
 
+def bucket_leg(idx32, spec, fx, shared, ef, target, steps):
+    """FES with r = 64 buckets (one per lane of a 64-wide wavefront; the paper's r = 32
+    matches a 32-wide warp) against the r = 32 index: recall at the same ef, the fastest
+    swept pair that reaches the target recall, and both indexes timed alternately at their
+    own pairs (the host stages' speed drifts within a run)."""
+    import dataclasses
+    sp = dataclasses.replace(spec, r=64)
+    sh = {k: shared[k] for k in ("V", "sub", "pivots")}
+    sh["init"] = fx["kmeans_init_choice"](spec.n_pivots, sp.r, spec.seed)
+    idx = build_index(sp, fx, "f32", sh)
+    _, _, rec_same = timed(idx, sp, fx, ef, 1, 0)
+    out = {"r": 64, "recall_at_r32_ef": {"ef_gpu": ef[0], "ef_cpu": ef[1], "recall": round(rec_same, 5)}}
+    ef64, curve = sweep(idx, sp, fx, target, sorted(set(sp.ef) | {40, 56}))  # finer near the target
+    out["curve"] = curve
+    if ef64 is not None:
+        best = {32: (0.0, None, None), 64: (0.0, None, None)}
+        for _ in range(2):
+            for r, ix, e in ((64, idx, ef64), (32, idx32, ef)):
+                dt, agg, rec = timed(ix, sp if r == 64 else spec, fx, e, steps, 1)
+                q = spec.queries * steps / dt
+                if q > best[r][0]:
+                    best[r] = (q, rec, agg)
+        for r, e in ((64, ef64), (32, ef)):
+            q, rec, agg = best[r]
+            out[f"r{r}_at_target"] = {"ef_gpu": e[0], "ef_cpu": e[1], "qps": round(q, 1), "recall": round(rec, 5),
+                                      "mean_n_dist3": round(agg["n_dist3"] / (spec.queries * steps), 1),
+                                      "fes_ms_per_step": round(agg["fes_ms"] / steps, 3)}
+    idx.close()
+    log(f"  buckets: { {k: v for k, v in out.items() if k != 'curve'} }")
+    return out
+
+
 def ratio_sweep(spec, fx, shared, ef, steps):
     """The paper's (rho, d_r / D) grid, compact layout with fp16 rows at a fixed ef: recall,
     QPS and HBM per point (opt-in: nine index builds)."""
@@ -635,6 +667,9 @@ def main():
             extra["top100"] = top100(idx, spec, fx, args.target)
             log("gpu-only special case")
             extra["gpu_only"] = gpu_only_leg(spec, fx, args.target, max(1, min(args.steps, 3)))
+            log("64 buckets")
+            extra["fes_64_buckets"] = bucket_leg(idx, spec, fx, shared, ef, args.target,
+                                                 max(1, min(args.steps, 3)))
         if form == "f16" and args.ratio_sweep:
             log("ratio sweep")
             extra["ratio_sweep"] = ratio_sweep(spec, fx, shared, ef, max(1, min(args.steps, 3)))
