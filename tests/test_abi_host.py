@@ -301,3 +301,14 @@ def test_hbm_model_hand_sums_and_planner_choice():
         with pytest.raises(pa.PilotannError) as e:
             pa.plan_memory(shape, 10 ** 12, [bad_rho], [bad_w])
         assert e.value.status == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it says so and exits before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2 and r.stdout == ""
+    assert "one GPU" in r.stderr
