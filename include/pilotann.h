@@ -427,8 +427,8 @@ typedef struct {
  *   n_p*(d_r + 4)                                 FP8 pivot codes and scales (FP8 form)
  *   m*(4*D + 4*d_r + 4 + 8*E + 8*ef_gpu + 16) + 4*(3*r + 2 + B)   search buffers (m > 0;
  *                                                 the 4*D term only without q_on_device)
- * Returns -1 for an invalid shape, rho outside (0, 1] or d_r outside 16..D or not a
- * multiple of 16. */
+ * Returns -1 for an invalid shape, rho outside (0, 1], or d_r outside 16..min(D,
+ * PA_MAX_DR) or not a multiple of 16. */
 int64_t pa_hbm_bytes(const pa_memory_shape* shape, double rho, int32_t d_r);
 
 /* Memory-bounded mode: from the candidate ratios rhos[n_rho] and widths d_rs[n_dr],

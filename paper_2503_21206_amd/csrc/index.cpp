@@ -151,7 +151,7 @@ int64_t index_hbm_model(const pa_memory_shape& s, double rho, int d_r) {
         s.R_sub < 1 || s.R_sub > 1024 || s.r < 1 || s.n_pivots < s.r || s.n_pivots % s.r != 0 || s.queries < 0 ||
         s.batch < 0 || s.ef_gpu < 1 || s.ef_gpu > PA_MAX_EF || s.E < 0 || s.E > PA_MAX_EF)
         return -1;
-    if (!(rho > 0.0 && rho <= 1.0) || d_r < 16 || d_r > s.dim || d_r % 16 != 0) return -1;
+    if (!(rho > 0.0 && rho <= 1.0) || d_r < 16 || d_r > s.dim || d_r > PA_MAX_DR || d_r % 16 != 0) return -1;
     const int64_t D = s.dim, dr = d_r, np = s.n_pivots, r = s.r, R = s.R_sub;
     const int64_t es = static_cast<int64_t>(dtype_size(s.xr_dtype));
     const int64_t ns = std::llround(rho * static_cast<double>(s.N));

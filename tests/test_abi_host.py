@@ -297,6 +297,9 @@ def test_hbm_model_hand_sums_and_planner_choice():
     with pytest.raises(pa.PilotannError) as e:
         pa.plan_memory(shape, cost[(0.1, 16)] - 1, rhos, widths)
     assert e.value.status == -4  # PA_EHBM: nothing fits
+    wide = pa.memory_shape(N=1000, dim=512, R_sub=8, n_pivots=64, r=4)
+    with pytest.raises(pa.PilotannError):
+        pa.hbm_bytes(wide, 0.25, 272)  # above the largest reduced width the library builds
     for bad_rho, bad_w in ((0.0, 16), (1.5, 16), (0.25, 24), (0.25, 48)):
         with pytest.raises(pa.PilotannError) as e:
             pa.plan_memory(shape, 10 ** 12, [bad_rho], [bad_w])
