@@ -436,8 +436,8 @@ int64_t pa_hbm_bytes(const pa_memory_shape* shape, double rho, int32_t d_r);
  * sample holds more of each query's answers for stage 1), and at that rho the largest
  * d_r.  Writes the pair and its bytes (any output may be NULL).  PA_EHBM when no pair
  * fits; PA_EINVAL for an invalid shape or candidate, or an empty candidate list.  An
- * index built with the chosen pair and hbm_budget as pa_params.hbm_budget then holds
- * exactly the predicted bytes. */
+ * index built with the chosen pair (and hbm_budget as pa_params.hbm_budget) and searched
+ * as the shape describes holds exactly the predicted bytes. */
 pa_status pa_plan_memory(const pa_memory_shape* shape, int64_t hbm_budget, const double* rhos, int32_t n_rho,
                          const int32_t* d_rs, int32_t n_dr, double* rho_out, int32_t* d_r_out,
                          int64_t* bytes_out);
