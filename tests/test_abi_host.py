@@ -315,3 +315,18 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120, cwd=root)
     assert r.returncode == 2 and r.stdout == ""
     assert "one GPU" in r.stderr
+
+
+def test_bench_roofline_counts_the_algorithmic_bytes():
+    """The beam kernel's algorithmic bytes per query: 4*d_r (query) + 4*E (entries) + 8*ef
+    (list out) + 4*R per expansion (adjacency row) + s*d_r per distance (reduced row)."""
+    import types
+    import bench
+    spec = types.SimpleNamespace(name="hand", queries=10, d_r=64, degree=32)
+    agg = {"n_exp1": 650, "n_dist1": 8670, "beam_launches": 2, "beam_ms": 1.0}
+    r = bench.roofline(spec, agg, 2, 64, 64, 4, "f32")
+    # 20 queries * (256 + 256 + 512) + 650 * 128 + 8670 * 256 = 20480 + 83200 + 2219520 bytes
+    # over two launches of 0.5 ms each
+    assert r["bytes_per_launch"] == (20480 + 83200 + 2219520) // 2
+    assert abs(r["achieved"] - 2323200 / 2 / 0.5e-3 / 1e9) < 0.05
+    assert r["peak"] == 8000.0 and r["traffic"] is None  # no profile for this workload
