@@ -133,6 +133,35 @@ def test_traverse_hand_examples(golden_dir):
         assert r["n_dist"] == c["n_dist"], c["name"]
 
 
+def test_near_tie_margin_hand_examples(golden_dir):
+    """The margin that excuses a divergence from the oracle, worked by hand: each case
+    isolates one kind of decision (initial resize, choice of the node to expand, resize
+    after an expansion, order of the final list, inner-product keys, width 2, an exact
+    tie), so a gap taken at the wrong position or between the wrong keys fails one."""
+    g = _load(golden_dir, "margin_examples.json")
+    for c in g["traverse"]:
+        rowptr, nbrs = _csr(c["rows"])
+        r = oracle.greedy_search(np.array(c["query"]), np.array(c["points"], dtype=np.float64), rowptr, nbrs,
+                                 c["ef"], c["entries"], c["metric"], width=c["width"])
+        assert r["ids"].tolist() == c["ids"], c["name"]
+        assert (r["n_exp"], r["n_dist"]) == (c["n_exp"], c["n_dist"]), c["name"]
+        num, den = c["margin"]
+        assert r["margin"] == num / den, (c["name"], r["margin"], num / den)
+    rt = g["route"]
+    cent = np.array(rt["centroids"], dtype=np.float64)
+    for c in rt["cases"]:
+        cl, gap = oracle.route(np.array(c["query"]), cent)
+        assert cl == c["cluster"], c["name"]
+        assert gap == c["gap"][0] / c["gap"][1], (c["name"], gap)
+    se = g["select_entries"]
+    P = np.array(se["pivots"], dtype=np.float64)
+    for c in se["cases"]:
+        ids, _, cl, margin = oracle.select_entries(np.array([c["query"]]), np.array(se["centroids"]),
+                                                   np.array(se["buckets"]), P, se["pivot_ids"], c["E"])
+        assert int(cl[0]) == c["cluster"] and ids[0].tolist() == c["entry_ids"], c["name"]
+        assert margin[0] == c["margin"][0] / c["margin"][1], (c["name"], margin[0])
+
+
 def _small_graph(n=600, dim=10, comps=3, seed=21, R=12):
     from synth.graph import build_graph, padded_to_csr
     X = gmm_points(seed, n, dim, comps)
