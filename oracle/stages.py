@@ -60,32 +60,53 @@ def final_traversal(q, X, rowptr, nbrs, cand_ids, cand_dists, visited, ef_cpu: i
     return ids, dists, res
 
 
+def _order_gap(keys) -> float:
+    """Smallest relative gap between neighbouring values of an ordered sequence."""
+    gap = np.inf
+    for a, b in zip(keys, keys[1:]):
+        gap = min(gap, abs(b - a) / max(abs(a), abs(b), 1e-300))
+    return gap
+
+
 def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets, pivot_vecs,
              pivot_ids, *, k: int, ef_gpu: int, ef_cpu: int, E: int, metric: str = "l2",
              refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True, bloom_log2=None,
-             use_final: bool = True, width: int = 1):
+             use_final: bool = True, width: int = 1, Qr=None, with_margin: bool = False):
     """All stages for every query; returns (ids [m][k], dists [m][k], counters [m][4]).
 
     counters = (stage-1 distances, stage-2 distances, stage-3 distances, stage-3 steps).
     use_final=False skips stage 3 and returns the best k of the stage-2 list by full
     distance (with every node sampled and d_r = D this is the GPU-only special case).
+
+    Qr: the reduced queries [m][d_r] to route and search with; by default q V computed
+    here in fp64.  Passing the reduced queries a library computed makes the comparison
+    stage-isolated from the projection on: both sides then start from the same vectors
+    (the projection itself is compared separately, against its own error bound).
+
+    with_margin=True appends margin [m]: per query, the smallest relative gap over every
+    comparison that decided its result (routing, the entry cut, each stage's Algorithm 1
+    decisions, and the order of the k returned keys).
     """
     if not use_final and not use_gpu_stage:
         raise ValueError("without the GPU stage the final traversal must run")
     Q = np.asarray(Q, dtype=np.float64)
-    Qr = project(Q, V)
-    entries, _, _, _ = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
+    Qr = project(Q, V) if Qr is None else np.asarray(Qr, dtype=np.float64)
+    entries, _, _, e_margin = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
     m = Q.shape[0]
     out_i = np.full((m, k), -1, dtype=np.int64)
     out_d = np.full((m, k), np.inf)
     counters = np.zeros((m, 4), dtype=np.int64)
+    margins = np.full(m, np.inf)
     for i in range(m):
+        margin = float(e_margin[i])
         if use_gpu_stage:
             g = gpu_stage(Qr[i], Xr, sub_rowptr, sub_nbrs, entries[i], ef_gpu, metric, bloom_log2, width)
             counters[i, 0] = g["n_dist"]
+            margin = min(margin, g["margin"])
             if use_refine:
                 r = refine(Q[i], X, sub_rowptr, sub_nbrs, g["ids"], ef_cpu, metric, refine_steps)
                 counters[i, 1] = r["n_dist"]
+                margin = min(margin, r["margin"])
                 c_ids, c_d, vis = r["ids"], r["dists"], r["visited"]
             else:
                 c_ids = g["ids"]
@@ -94,8 +115,12 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
                 vis = set(int(v) for v in c_ids)
             if use_final:
                 ids, d, f = final_traversal(Q[i], X, rowptr, nbrs, c_ids, c_d, vis, ef_cpu, k, metric)
+                margin = min(margin, f["margin"])
             else:
-                order = sorted(range(len(c_ids)), key=lambda j: (float(c_d[j]), int(c_ids[j])))[:min(ef_cpu, k)]
+                order = sorted(range(len(c_ids)), key=lambda j: (float(c_d[j]), int(c_ids[j])))
+                # the cut after the k-th key and the order of the k kept
+                margin = min(margin, _order_gap([float(c_d[j]) for j in order[:min(ef_cpu, k) + 1]]))
+                order = order[:min(ef_cpu, k)]
                 ids = np.full(k, -1, dtype=np.int64)
                 d = np.full(k, np.inf)
                 ids[:len(order)] = [int(c_ids[j]) for j in order]
@@ -104,6 +129,7 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
         else:
             ef = max(ef_cpu, k)
             f = greedy_search(Q[i], X, rowptr, nbrs, ef, entries[i], metric)
+            margin = min(margin, f["margin"])
             ids = np.full(k, -1, dtype=np.int64)
             d = np.full(k, np.inf)
             t = min(k, f["ids"].size)
@@ -111,4 +137,7 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
         counters[i, 2] = f["n_dist"]
         counters[i, 3] = f["n_exp"]
         out_i[i], out_d[i] = ids, d
+        margins[i] = margin
+    if with_margin:
+        return out_i, out_d, counters, margins
     return out_i, out_d, counters

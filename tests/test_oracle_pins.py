@@ -410,6 +410,31 @@ def test_stages_hand_example(golden_dir):
     assert f["n_exp"] == g["final_n_exp"] and f["n_dist"] == g["final_n_dist"]
 
 
+def test_pipeline_margin_hand_example(golden_dir):
+    """The whole search's margin combines the entry cut with every stage's decisions."""
+    g = _load(golden_dir, "pipeline_margin_example.json")
+    X = np.array(g["points"], dtype=np.float64)
+    V = np.array(g["V"], dtype=np.float64)
+    sr, sn = _csr(g["sub_rows"])
+    fr, fn = _csr(g["full_rows"])
+    P = X[g["pivot_ids"]]
+    for c in g["cases"]:
+        ids, d, cnt, margin = oracle.pipeline(np.array([g["query"]]), X, V, fr, fn, sr, sn, X @ V,
+                                              np.array(g["centroids"]), np.array(g["buckets"]), P, g["pivot_ids"],
+                                              k=g["k"], ef_gpu=g["ef_gpu"], ef_cpu=g["ef_cpu"], E=g["E"],
+                                              use_gpu_stage=c["use_gpu_stage"], with_margin=True)
+        assert ids[0].tolist() == c["ids"] and d[0].tolist() == c["dists"], c["name"]
+        assert cnt[0].tolist() == c["counters"], (c["name"], cnt[0])
+        assert margin[0] == c["margin"][0] / c["margin"][1], (c["name"], margin[0])
+        # the same search started from given reduced queries (here q V itself)
+        ids2, _, _, m2 = oracle.pipeline(np.array([g["query"]]), X, V, fr, fn, sr, sn, X @ V,
+                                         np.array(g["centroids"]), np.array(g["buckets"]), P, g["pivot_ids"],
+                                         k=g["k"], ef_gpu=g["ef_gpu"], ef_cpu=g["ef_cpu"], E=g["E"],
+                                         use_gpu_stage=c["use_gpu_stage"], with_margin=True,
+                                         Qr=np.array([g["query"]]) @ V)
+        assert ids2[0].tolist() == c["ids"] and m2[0] == margin[0]
+
+
 def test_refine_without_steps_is_a_rerank_by_full_distance():
     X, rowptr, nbrs = _small_graph(seed=81)
     q = gmm_points(82, 1, 10, 3, stream_offset=1)[0]
