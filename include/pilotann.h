@@ -106,14 +106,18 @@ pa_status pa_fit_projection(const float* X_host, int64_t N, int32_t D, int32_t d
                             int32_t center, float* V_host, double* evals_host,
                             double* mean_host);
 
-/* Y_dev [n][d_r] = X_dev [n][D] * V_dev [D][d_r] on MFMA (fp32 inputs, fp32 accumulate),
- * stored as y_dtype (PA_F32 / PA_F16 / PA_BF16, round-to-nearest-even).  The reduced
- * vectors x_primary of section 4.1.  d_r % 16 == 0, d_r <= PA_MAX_DR, D <= 4096. */
+/* Y_dev [n][d_r] = X_dev [n][D] * V_dev [D][d_r]: the reduced vectors x_primary of section
+ * 4.1.  Each fp32 output is the exact product rounded once to fp32 (compensated fp32
+ * accumulation; it can differ by one ulp only where the exact value lies within about
+ * 2^-44 of sum |x_k v_k| of a rounding midpoint), independent of n and of the other rows;
+ * PA_F16 / PA_BF16 outputs are that fp32 value rounded to nearest even.
+ * d_r % 16 == 0, d_r <= PA_MAX_DR, D <= 4096. */
 pa_status pa_project(const float* X_dev, int64_t n, int32_t D, const float* V_dev,
                      int32_t d_r, void* Y_dev, int32_t y_dtype, void* stream);
 
 /* Query projection fused with FES routing (section 5: a query is routed to the cluster
- * whose centroid is nearest).  Qr_dev [m][d_r] fp32 = Q_dev [m][D] * V_dev; cluster_dev
+ * whose centroid is nearest).  Qr_dev [m][d_r] fp32 = Q_dev [m][D] * V_dev, rounded as in
+ * pa_project; cluster_dev
  * [m] int32 = argmin_c ||q_r - centroid_c||^2 over centroids_dev [r][d_r] (fp32), ties
  * to the lowest c.  1 <= r <= 64. */
 pa_status pa_project_route(const float* Q_dev, int64_t m, int32_t D, const float* V_dev,

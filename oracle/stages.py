@@ -78,10 +78,10 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
     use_final=False skips stage 3 and returns the best k of the stage-2 list by full
     distance (with every node sampled and d_r = D this is the GPU-only special case).
 
-    Qr: the reduced queries [m][d_r] to route and search with; by default q V computed
-    here in fp64.  Passing the reduced queries a library computed makes the comparison
-    stage-isolated from the projection on: both sides then start from the same vectors
-    (the projection itself is compared separately, against its own error bound).
+    Qr: the reduced queries [m][d_r] to route and search with; by default q^T V_d computed
+    here exactly (fp64) and rounded once to fp32: the search computes in single precision
+    (section 6.1), and the reduced query is held like the reduced base vectors X_r, which
+    the caller passes already rounded.
 
     with_margin=True appends margin [m]: per query, the smallest relative gap over every
     comparison that decided its result (routing, the entry cut, each stage's Algorithm 1
@@ -90,7 +90,7 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
     if not use_final and not use_gpu_stage:
         raise ValueError("without the GPU stage the final traversal must run")
     Q = np.asarray(Q, dtype=np.float64)
-    Qr = project(Q, V) if Qr is None else np.asarray(Qr, dtype=np.float64)
+    Qr = as_f32(project(Q, V)) if Qr is None else np.asarray(Qr, dtype=np.float64)
     entries, _, _, e_margin = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
     m = Q.shape[0]
     out_i = np.full((m, k), -1, dtype=np.int64)

@@ -1,4 +1,4 @@
-// Projection to the SVD subspace (section 4.1: x_primary = x^T V_d) on MFMA, the FES
+// Projection to the SVD subspace (section 4.1: x_primary = x^T V_d), correctly rounded, the FES
 // routing of a reduced query to its nearest coarse centroid (section 5), and the FP64
 // second-moment accumulation that fixes V (the only FP64 work on the GPU).
 #include <hip/hip_runtime.h>
@@ -9,15 +9,23 @@
 namespace pa {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------- projection GEMM
-// Block: 256 threads = 4 waves, 64 output rows x all d_r columns.  The K loop stages a
-// 64x16 slice of X and a 16 x d_r slice of V in LDS; each wave multiplies its 16 rows with
-// v_mfma_f32_16x16x4_f32 (A: lane l holds A[l%16][l/16]; B: lane l holds B[l/16][l%16];
-// D: lane l holds rows 4*(l/16)..+3 of column l%16).
-constexpr int kBM = 64;
-constexpr int kBK = 16;
+// ---------------------------------------------------------------- projection
+// y = x^T V_d for a block of 64 rows x 64 columns (256 threads, 4 x 4 outputs each).  The
+// method compares single-precision distances (section 6.1), and every later stage sees
+// only the reduced vectors, so the projection's fp32 output is defined as the exact
+// product rounded once: each output is a float-float (hi + lo) sum of exact products
+// (fma two-product, two-sum), renormalised after every K slice of 16, and rounded to fp32
+// at the end; fp16 / bf16 outputs are that fp32 value rounded to nearest even.  The result
+// is the correctly rounded value except when the exact sum lies within the pair's error
+// (about 2^-44 of sum |x_k v_k|) of a midpoint, and does not depend on the batch around a
+// row.  A plain fp32 MFMA product would differ from it in the last bits of most outputs,
+// and those bits move near-tied decisions of every stage after it.  The product is a
+// small part of a search (2 m D d_r flops against the traversal's gathers), so it runs on
+// the vector ALUs; the FES distance products stay on MFMA (their fp32 results only
+// pre-select candidates that are re-scored exactly).
+constexpr int kPM = 64;  // rows per block
+constexpr int kPN = 64;  // columns per block
+constexpr int kPK = 16;  // K slice staged in LDS
 
 __device__ __forceinline__ uint16_t f32_to_f16_bits(float v) {
     _Float16 h = static_cast<_Float16>(v);  // round to nearest even
@@ -35,56 +43,68 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
 __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ X, int64_t n, int D,
                                                       const float* __restrict__ V, int d_r, void* Y,
                                                       int y_dtype) {
-    __shared__ float As[kBM][kBK + 1];
-    __shared__ float Bs[kBK][PA_MAX_DR + 4];
+    __shared__ float Xs[kPK][kPM + 4];  // X slice, transposed: Xs[k][row]
+    __shared__ float Vs[kPK][kPN + 4];  // V slice: Vs[k][column]
     const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int w = t >> 6;
-    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kBM;
-    const int nb = d_r >> 4;
-    f32x4 acc[PA_MAX_DR / 16];
+    const int tr = t >> 4;  // rows 4*tr .. 4*tr+3 of the block
+    const int tc = t & 15;  // columns tc, tc+16, tc+32, tc+48 of the block
+    const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kPM;
+    const int col0 = blockIdx.y * kPN;
+    ff32 acc[4][4];
 #pragma unroll
-    for (int c = 0; c < PA_MAX_DR / 16; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = ff32{0.0f, 0.0f};
 
-    for (int k0 = 0; k0 < D; k0 += kBK) {
-        {
+    for (int k0 = 0; k0 < D; k0 += kPK) {
+        {  // X: 64 rows x 16 k, four per thread
             const int r = t >> 2;
             const int c = (t & 3) * 4;
             const int64_t gr = row0 + r;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int k = k0 + c + e;
-                As[r][c + e] = (gr < n && k < D) ? X[gr * D + k] : 0.0f;
+                Xs[c + e][r] = (gr < n && k < D) ? X[gr * D + k] : 0.0f;
             }
         }
-        for (int idx = t; idx < kBK * d_r; idx += 256) {
-            const int kk = idx / d_r;
-            const int j = idx - kk * d_r;
-            Bs[kk][j] = (k0 + kk < D) ? V[static_cast<int64_t>(k0 + kk) * d_r + j] : 0.0f;
+        {  // V: 16 k x 64 columns, four per thread
+            const int kk = t >> 4;
+            const int j = (t & 15) * 4;
+            const int k = k0 + kk;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int col = col0 + j + e;
+                Vs[kk][j + e] = (k < D && col < d_r) ? V[static_cast<int64_t>(k) * d_r + col] : 0.0f;
+            }
         }
         __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kPK; ++kk) {
+            const float4 xv = *reinterpret_cast<const float4*>(&Xs[kk][4 * tr]);
+            const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            float vs[4];
 #pragma unroll
-        for (int kk = 0; kk < kBK; kk += 4) {
-            const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int j = 0; j < 4; ++j) vs[j] = Vs[kk][tc + 16 * j];
 #pragma unroll
-            for (int c = 0; c < PA_MAX_DR / 16; ++c) {
-                if (c < nb) {
-                    const float b = Bs[kk + (lane >> 4)][c * 16 + (lane & 15)];
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
-                }
-            }
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ff_add_prod(acc[i][j], xs[i], vs[j]);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = ff_norm(acc[i][j]);
         __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < PA_MAX_DR / 16; ++c) {
-        if (c >= nb) continue;
-        const int col = c * 16 + (lane & 15);
+    for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 4 * tr + i;
+        if (row >= n) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t row = row0 + w * 16 + 4 * (lane >> 4) + i;
-            if (row >= n) continue;
-            const float v = acc[c][i];
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + tc + 16 * j;
+            if (col >= d_r) continue;
+            const float v = acc[i][j].hi;  // normalised: hi is hi + lo rounded to fp32
             const int64_t off = row * d_r + col;
             if (y_dtype == PA_F32) static_cast<float*>(Y)[off] = v;
             else if (y_dtype == PA_F16) static_cast<uint16_t*>(Y)[off] = f32_to_f16_bits(v);
@@ -210,8 +230,9 @@ __global__ __launch_bounds__(256) void sum_chunks_kernel(const double* __restric
 void launch_project(const float* X, int64_t n, int D, const float* V, int d_r, void* Y, int y_dtype,
                     const float* centroids, int r, int32_t* cluster, hipStream_t s) {
     if (n == 0) return;
-    const int blocks = static_cast<int>((n + kBM - 1) / kBM);
-    hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, s, X, n, D, V, d_r, Y, y_dtype);
+    const int blocks = static_cast<int>((n + kPM - 1) / kPM);
+    const int col_blocks = (d_r + kPN - 1) / kPN;
+    hipLaunchKernelGGL(project_kernel, dim3(blocks, col_blocks), dim3(256), 0, s, X, n, D, V, d_r, Y, y_dtype);
     PA_HIP(hipGetLastError());
     if (centroids != nullptr) {
         const int rb = static_cast<int>((n + 3) / 4);
