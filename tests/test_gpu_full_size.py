@@ -1,7 +1,10 @@
 """Parity at the bench's full size (1,000,000 x 128, 10,000 queries, d_r 64, 4,096 pivots
 in 32 buckets, ef 64) in the launch configuration the bench times: all 10,000 queries of
-the traversal in one launch.  The oracle recomputes sampled queries one by one; the rest
-is checked through properties that hold at any size."""
+the traversal in one launch.  The oracle recomputes 1,000 sampled queries one by one
+(spread over the host cores); the rest is checked through properties that hold at any
+size.  A second subgraph at sampling ratio 0.5 checks the whole pipeline there too (the
+memory-bounded sweep's recall is lower at 0.5 than at 0.25 on this workload; the oracle
+decides whether that is the method on this fixture or the library)."""
 
 import numpy as np
 import pytest
@@ -11,13 +14,29 @@ import paper_2503_21206_amd as pa
 from synth import SPECS, base_vectors, kmeans_init_choice, node_order, pivot_choice, query_vectors
 from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
 from synth.knn import exact_knn
-from tests.gpu_checks import _t, say, traverse_check
-from tests.parity import TIE, DistTally
+from tests import oracle_jobs
+from tests.gpu_checks import _t, pipeline_check, say, traverse_check
+from tests.parity import TIE, DistTally, ulp_diff
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SAMPLE = np.array([0, 1, 2, 3, 517, 1234, 2048, 3333, 4095, 4096, 5000, 6001, 7777, 8191, 8192, 9000, 9998, 9999])
+# 1,000 queries: both ends of the launch and an even spread over it
+SAMPLE = np.unique(np.concatenate([np.arange(0, 10_000, 10), [1, 2, 3, 4095, 4096, 8191, 8192, 9998, 9999]]))
+
+
+def _sub_tables(w, mask):
+    """Subgraph over the sampled rows, pivots and the oracle's buckets, entries for every query."""
+    s = w["spec"]
+    sr, sn = build_subgraph_csr(w["X"], mask, s.degree, device="cuda")
+    S = np.nonzero(mask)[0]
+    deg = sr[1:] - sr[:-1]
+    pivots = pivot_choice(S[deg[S] > 0], s.n_pivots, s.seed)
+    init = kmeans_init_choice(s.n_pivots, s.r, s.seed)
+    P = w["Xr32"][pivots].astype(np.float64)
+    buckets, cent = oracle.balanced_kmeans(P, s.r, init)
+    return dict(mask=mask, sr=sr, sn=sn, pivots=pivots, init=init, P=P, buckets=buckets,
+                cent=cent.astype(np.float32), sub_adj=oracle.padded_from_csr(sr, sn, int(deg.max())))
 
 
 @pytest.fixture(scope="module")
@@ -30,53 +49,82 @@ def full():
     X, Q = base_vectors(s), query_vectors(s)
     adj = build_graph(X, s.degree, device="cuda")
     rp, nb = padded_to_csr(adj)
-    mask = oracle.sample_nodes(rp, nb, node_order(s.n, s.seed), round(s.rho * s.n), s.sample_mode)
-    sr, sn = build_subgraph_csr(X, mask, s.degree, device="cuda")
     say("fixture: oracle projection (fp64 covariance, eigendecomposition) and reduced vectors")
     V64, _, _ = oracle.fit_projection(X, s.d_r, s.metric)
     V32 = V64.astype(np.float32)
     Xr32 = oracle.project(X, V32).astype(np.float32)
     Qr32 = oracle.project(Q, V32).astype(np.float32)
-    S = np.nonzero(mask)[0]
-    deg = sr[1:] - sr[:-1]
-    pivots = pivot_choice(S[deg[S] > 0], s.n_pivots, s.seed)
-    init = kmeans_init_choice(s.n_pivots, s.r, s.seed)
-    P = Xr32[pivots].astype(np.float64)
-    buckets, cent = oracle.balanced_kmeans(P, s.r, init)
-    R_sub = int(deg.max())
+    w = dict(spec=s, X=X, Q=Q, rp=rp, nb=nb, V32=V32, Xr32=Xr32, Qr32=Qr32)
+    mask = oracle.sample_nodes(rp, nb, node_order(s.n, s.seed), round(s.rho * s.n), s.sample_mode)
+    w.update(_sub_tables(w, mask))
     say("fixture: oracle entries for every query")
-    ent, _, _, _ = oracle.select_entries(Qr32, cent, buckets, P, pivots, 64)
-    return dict(spec=s, X=X, Q=Q, rp=rp, nb=nb, mask=mask, sr=sr, sn=sn, V32=V32, Xr32=Xr32, Qr32=Qr32,
-                pivots=pivots, init=init, P=P, buckets=buckets, cent=cent, ent=ent,
-                sub_adj=oracle.padded_from_csr(sr, sn, R_sub))
+    ent, _, cl, _ = oracle.select_entries(Qr32, w["cent"].astype(np.float64), w["buckets"], w["P"], w["pivots"], 64)
+    w.update(ent=ent, cl=cl)
+    return w
+
+
+def _index(w, sub, xr="f32", compact=False):
+    s = w["spec"]
+    idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype=xr, r=s.r, compact=compact))
+    idx.set_data(w["X"], w["rp"], w["nb"])
+    idx.set_projection(w["V32"])
+    idx.build_subgraph(sub["mask"], sub["sr"], sub["sn"])
+    idx.build_entries(sub["pivots"], sub["init"], 10)
+    _, b, c = idx.state()
+    assert (b == sub["pivots"][sub["buckets"]]).all() and (c.view(np.uint32) == sub["cent"].view(np.uint32)).all()
+    return idx
+
+
+def _arrays(w, sub, Xr=None):
+    return dict(Q=w["Q"], Qr=w["Qr32"], X=w["X"], V=w["V32"], rp=w["rp"], nb=w["nb"], sr=sub["sr"], sn=sub["sn"],
+                Xr=w["Xr32"] if Xr is None else Xr, cent=sub["cent"], buckets=sub["buckets"],
+                P=sub["P"].astype(np.float32), pivots=sub["pivots"])
+
+
+def test_projection_full_size(full):
+    say("pa_project_route of the 10,000 queries and pa_project of the first 200,000 base rows")
+    w = full
+    Qr, cl = pa.project_route(_t(w["Q"], "cuda"), _t(w["V32"], "cuda"), _t(w["cent"], "cuda"))
+    u = ulp_diff(Qr.cpu().numpy(), w["Qr32"])
+    assert (u <= 1).all() and (u != 0).mean() <= 1e-4, (u != 0).mean()
+    cl = cl.cpu().numpy()
+    for i in np.nonzero(cl != w["cl"])[0]:  # routed differently only at a near tie
+        _, gap = oracle.route(w["Qr32"][i], w["cent"].astype(np.float64))
+        assert gap <= TIE, (i, gap)
+    assert (cl != w["cl"]).sum() <= 10
+    y = pa.project(_t(w["X"][:200_000], "cuda"), _t(w["V32"], "cuda"), "f32").cpu().numpy()
+    u = ulp_diff(y, w["Xr32"][:200_000])
+    say(f"  queries: {(cl != w['cl']).sum()} routed differently; base rows: {(u != 0).mean():.2e} one ulp off")
+    assert (u <= 1).all() and (u != 0).mean() <= 1e-4
 
 
 def test_fes_full_size(full):
-    say("select_entries: 10,000 queries, one launch; sampled rows against the oracle")
+    say(f"select_entries: 10,000 queries, one launch; {SAMPLE.size} rows against the oracle")
     w = full
     E = 64
     EV = w["P"][w["buckets"]].astype(np.float32)
     EVn = (EV.astype(np.float64) ** 2).sum(-1).astype(np.float32)
     EVid = w["pivots"][w["buckets"]].astype(np.int32)
     Qs = w["Qr32"][SAMPLE]
-    oi, od, ocl, margin = oracle.select_entries(Qs, w["cent"], w["buckets"], w["P"], w["pivots"], E)
-    cl_all = np.zeros(w["Q"].shape[0], dtype=np.int32)
-    cl_all[SAMPLE] = ocl  # the other rows take bucket 0: a full-size launch, checked on the sample
-    ids, d = pa.select_entries(_t(w["Qr32"], "cuda"), _t(cl_all, "cuda"), _t(EV, "cuda"), _t(EVn, "cuda"),
-                               _t(EVid, "cuda"), E)
+    oi, od, _, margin = oracle.select_entries(Qs, w["cent"].astype(np.float64), w["buckets"], w["P"], w["pivots"], E)
+    ids, d = pa.select_entries(_t(w["Qr32"], "cuda"), _t(w["cl"].astype(np.int32), "cuda"), _t(EV, "cuda"),
+                               _t(EVn, "cuda"), _t(EVid, "cuda"), E)
     ids, d = ids.cpu().numpy()[SAMPLE], d.cpu().numpy()[SAMPLE]
     tally = DistTally()
+    bad = 0
     for j in range(SAMPLE.size):
         if not (ids[j] == oi[j]).all():
             assert margin[j] <= TIE
+            bad += 1
             continue
         tally.check(d[j], od[j], int(SAMPLE[j]))
     tally.done()
+    assert bad <= max(1, SAMPLE.size // 1000)
 
 
 @pytest.mark.parametrize("form", ["f32", "f16"])
 def test_traversal_full_size(full, form):
-    say(f"gpu_traverse {form}: 10,000 queries in one launch, ef 64; {SAMPLE.size} sampled against the oracle")
+    say(f"gpu_traverse {form}: 10,000 queries in one launch, ef 64; {SAMPLE.size} against the oracle")
     w = full
     ent = w["ent"]
     xr = w["Xr32"] if form == "f32" else w["Xr32"].astype(np.float16).astype(np.float32)
@@ -93,28 +141,44 @@ def test_traversal_full_size(full, form):
         row = ids[i][ids[i] >= 0]
         assert np.unique(row).size == row.size and w["mask"][row].all()
         assert (np.diff(d[i][: row.size].astype(np.float64)) >= 0).all()
-    traverse_check("cuda", w, xr, Xd, ent, 64, SAMPLE, outputs=(ids[SAMPLE], d[SAMPLE], cnt[SAMPLE]))
+    refs = oracle_jobs.traverse(w["Qr32"], xr.astype(np.float64), w["sr"], w["sn"], ent, SAMPLE, 64)
+    traverse_check("cuda", w, xr, Xd, ent, 64, SAMPLE, outputs=(ids[SAMPLE], d[SAMPLE], cnt[SAMPLE]), refs=refs)
 
 
 def test_search_full_size(full):
-    say("Index.search: 10,000 queries (bench configuration); recall and exact final distances")
+    say(f"Index.search: 10,000 queries (bench configuration); {SAMPLE.size} against the oracle pipeline")
     w = full
-    s = w["spec"]
-    idx = pa.Index(pa.IndexConfig(dim=s.dim, d_r=s.d_r, metric=s.metric, xr_dtype="f32", r=s.r))
-    idx.set_data(w["X"], w["rp"], w["nb"])
-    idx.set_projection(w["V32"])
-    idx.build_subgraph(w["mask"], w["sr"], w["sn"])
-    idx.build_entries(w["pivots"], w["init"], 10)
-    Qd = _t(w["Q"], "cuda")
-    ids, d, cnt, st = idx.search(w["Q"], 10, 64, 64, with_counters=True, Q_dev=Qd)
+    idx = _index(w, w)
+    ids, d, cnt, st = idx.search(w["Q"], 10, 64, 64, with_counters=True)
     assert st["beam_launches"] == 1
     gt, _ = exact_knn(w["X"], w["Q"], 10, device="cuda")
     rec = oracle.recall_at_k(ids, gt, 10)
     say(f"  recall@10 {rec:.4f}")
-    assert rec >= 0.94  # the bench reaches 0.951 at this ef with its own projection
-    tally = DistTally()
+    assert rec >= 0.94  # the bench reaches 0.951 at this ef
     for i in range(0, w["Q"].shape[0], 50):
-        tally.check(d[i], oracle.as_f32(oracle.delta_many(w["Q"][i], w["X"][ids[i]])), i)
         assert (np.diff(d[i].astype(np.float64)) >= 0).all()
-    tally.done()
+    ref, = oracle_jobs.pipeline(_arrays(w, w), [(SAMPLE, dict(k=10, ef_gpu=64, ef_cpu=64, E=64))])
+    pipeline_check(ids[SAMPLE], d[SAMPLE], ref, "1M search, ef 64/64", cnt[SAMPLE])
+    say(f"  oracle recall@10 on the sample {oracle.recall_at_k(ref[0], gt[SAMPLE], 10):.4f}, "
+        f"library {oracle.recall_at_k(ids[SAMPLE], gt[SAMPLE], 10):.4f}")
+    idx.close()
+
+
+def test_sampling_ratio_half_matches_the_oracle(full):
+    """At rho = 0.5 the recall drops below rho = 0.25 on this workload; the oracle, run on
+    the same fixture, must show the same lists and the same drop."""
+    w = full
+    s = w["spec"]
+    say("rho = 0.5: subgraph, entries, library search (compact fp16 layout) and the oracle on 300 queries")
+    mask = oracle.sample_nodes(w["rp"], w["nb"], node_order(s.n, s.seed), round(0.5 * s.n), s.sample_mode)
+    sub = _sub_tables(w, mask)
+    idx = _index(w, sub, "f16", compact=True)
+    rows = SAMPLE[::3][:300]
+    ids, d, cnt, _ = idx.search(w["Q"], 10, 64, 64, with_counters=True)
+    xr16 = w["Xr32"].astype(np.float16).astype(np.float32)
+    ref, = oracle_jobs.pipeline(_arrays(w, sub, Xr=xr16), [(rows, dict(k=10, ef_gpu=64, ef_cpu=64, E=64))])
+    pipeline_check(ids[rows], d[rows], ref, "1M search at rho 0.5, compact fp16", cnt[rows])
+    gt, _ = exact_knn(w["X"], w["Q"], 10, device="cuda")
+    say(f"  recall@10 at rho 0.5: library {oracle.recall_at_k(ids, gt, 10):.4f} (all queries), "
+        f"oracle {oracle.recall_at_k(ref[0], gt[rows], 10):.4f} (sample)")
     idx.close()
