@@ -176,6 +176,23 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
                             const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
                             int32_t metric, int32_t* ids_dev, float* d_dev, void* stream);
 
+/* Allocation-free variant of pa_select_entries, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, layouts and results as pa_select_entries (the same kernels
+ * run); the scratch that pa_select_entries allocates per call (3 r + 2 + m int32: the
+ * grouping header and the query permutation) lives instead in a static device array of
+ * 3 * 64 + 2 + 262,144 int32 (about 1 MiB) per GPU, held until the process ends; the
+ * kernels write every scratch word they read before reading it, so nothing needs
+ * clearing.  m > 262,144 -> PA_EINVAL.  The call makes no device allocation and frees
+ * nothing.  Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams or host threads without ordering) race and must be serialised by
+ * the caller.  pa_device_init looks the array's device address up; otherwise the first
+ * call on a device does, with that device current. */
+pa_status pa_select_entries_noalloc(const float* Qr_dev, const int32_t* cluster_dev, int64_t m,
+                                    int32_t d, const float* EV_dev, const float* EVnorm_dev,
+                                    const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
+                                    int32_t metric, int32_t* ids_dev, float* d_dev, void* stream);
+
 /* FP8 encoding of the entry pivots (the precision form of fast entry selection): for every
  * row of X_host [n][d] fp32, scales_host[i] = max_j |x_ij| / 448 (1 for an all-zero row) and
  * codes_host[i][j] = e4m3(x_ij / scales_host[i]) with round-to-nearest-even (OCP e4m3,

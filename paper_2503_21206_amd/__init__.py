@@ -101,6 +101,7 @@ _SIGS = {
     "pa_pack_adjacency": [_I64, _P, _P, _I32, _P, _P],
     "pa_build_entries": [_P, _I32, _I32, _I32, _P, _I32, _P, _P],
     "pa_select_entries": [_P, _P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P],
+    "pa_select_entries_noalloc": [_P, _P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P],
     "pa_gpu_traverse": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P],
     "pa_gpu_traverse_bloom": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
                               _P],
@@ -331,6 +332,24 @@ def select_entries(Qr, cluster, EV, EVnorm, EVid, E: int, metric: str = "l2", st
                                    _dev(EV, torch.float32, "EV"), _dev(EVnorm, torch.float32, "EVnorm"),
                                    _dev(EVid, torch.int32, "EVid"), r, n_b, E, METRICS[metric], _dev(ids),
                                    _dev(dist), _stream(stream)))
+    return ids, dist
+
+
+def select_entries_noalloc(Qr, cluster, EV, EVnorm, EVid, ids, dist, E: int, metric: str = "l2", stream=None):
+    """pa_select_entries_noalloc: as select_entries, into caller-owned ids [m][E] int32 and
+    dist [m][E] fp32 device tensors; the library allocates nothing on the device."""
+    import torch
+    m, d = Qr.shape
+    r, n_b = EVid.shape
+    if tuple(EV.shape) != (r, n_b, d) or tuple(EVnorm.shape) != (r, n_b) or tuple(cluster.shape) != (m,):
+        raise ValueError("EV [r][n_b][d], EVnorm [r][n_b] and cluster [m] must match Qr and EVid")
+    if tuple(ids.shape) != (m, E) or tuple(dist.shape) != (m, E):
+        raise ValueError("ids and dist must be [m][E]")
+    _check(lib().pa_select_entries_noalloc(_dev(Qr, torch.float32, "Qr"), _dev(cluster, torch.int32, "cluster"), m,
+                                           d, _dev(EV, torch.float32, "EV"), _dev(EVnorm, torch.float32, "EVnorm"),
+                                           _dev(EVid, torch.int32, "EVid"), r, n_b, E, METRICS[metric],
+                                           _dev(ids, torch.int32, "ids"), _dev(dist, torch.float32, "dist"),
+                                           _stream(stream)))
     return ids, dist
 
 

@@ -291,7 +291,7 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pa_abi_version(void) { return 9; }
+int32_t pa_abi_version(void) { return 10; }
 
 pa_status pa_device_init(int32_t device) {
     return guarded([&] {
@@ -304,6 +304,7 @@ pa_status pa_device_init(int32_t device) {
         std::string arch = prop.gcnArchName;
         require(arch.rfind("gfx950", 0) == 0, "device " + std::to_string(device) + " is " + arch + ", not gfx950",
                 PA_EUNSUPPORTED);
+        static_scratch_for_device(device);  // device address of the allocation-free entry point's scratch
     });
 }
 
@@ -432,6 +433,28 @@ pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int
         launch_select_entries(Qr_dev, cluster_dev, m, d, EV_dev, EVnorm_dev, EVid_dev, r, n_b, E, metric, ids_dev,
                               d_dev, scratch, s);
         PA_HIP(hipFreeAsync(scratch, s));
+    });
+}
+
+pa_status pa_select_entries_noalloc(const float* Qr_dev, const int32_t* cluster_dev, int64_t m, int32_t d,
+                                    const float* EV_dev, const float* EVnorm_dev, const int32_t* EVid_dev, int32_t r,
+                                    int32_t n_b, int32_t E, int32_t metric, int32_t* ids_dev, float* d_dev,
+                                    void* stream) {
+    return guarded([&] {
+        require(m >= 0, "m must be >= 0");
+        require(m <= static_scratch_max_queries(),
+                "pa_select_entries_noalloc takes at most " + std::to_string(static_scratch_max_queries()) +
+                    " queries per call (its static scratch holds that many)");
+        require(d > 0 && d % 16 == 0 && d <= PA_MAX_DR, "d must be a multiple of 16 in [16, 256]");
+        require(r >= 1 && r <= 64 && n_b >= 1 && E >= 1 && E <= PA_MAX_EF, "need 1<=r<=64, n_b>=1, 1<=E<=512");
+        require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
+        if (m == 0) return;
+        require(Qr_dev && cluster_dev && EV_dev && EVnorm_dev && EVid_dev && ids_dev && d_dev, "null pointer");
+        int dev = 0;
+        PA_HIP(hipGetDevice(&dev));
+        int32_t* scratch = static_scratch_for_device(dev);  // written in full before it is read
+        launch_select_entries(Qr_dev, cluster_dev, m, d, EV_dev, EVnorm_dev, EVid_dev, r, n_b, E, metric, ids_dev,
+                              d_dev, scratch, as_stream(stream));
     });
 }
 

@@ -120,6 +120,10 @@ void launch_select_entries(const float* Qr, const int32_t* cluster, int64_t m, i
                            int E, int metric, int32_t* ids, float* dists, int32_t* scratch_i32,
                            hipStream_t s);
 size_t select_entries_scratch_ints(int64_t m, int r);
+// Entry selection's static scratch on `device` (which must be current), for the
+// allocation-free entry point; it holds the scratch of this many queries.
+int32_t* static_scratch_for_device(int device);
+int64_t static_scratch_max_queries();
 void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
                                    const uint8_t* EV8, const float* EVscale, const float* EVnorm,
                                    const int32_t* EVid, int r, int n_b, int E, int K, int metric, int32_t* ids,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "ffloat.hpp"
@@ -360,6 +361,39 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
 }  // namespace
 
 size_t select_entries_scratch_ints(int64_t m, int r) { return static_cast<size_t>(3 * r + 2 + m); }
+
+// ---------------------------------------------------------------- static scratch
+// For callers that cannot allocate device memory: entry selection's scratch (the
+// grouping header and the query permutation) in a fixed device array, one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in symbol); it uses the device address looked up once per
+// device with that device current.
+constexpr int64_t kStaticFesQueries = 262144;
+constexpr int64_t kStaticFesInts = 3 * kMaxClusters + 2 + kStaticFesQueries;
+static __device__ __align__(256) int32_t scratch[kStaticFesInts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int64_t static_scratch_max_queries() { return kStaticFesQueries; }
+
+int32_t* static_scratch_for_device(int device) {
+    require(device >= 0 && device < kMaxDevices, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device] == nullptr) {
+        int cur = -1;
+        PA_HIP(hipGetDevice(&cur));
+        require(cur == device, "the static scratch must be looked up with its device current", PA_EINTERNAL);
+        void* p = nullptr;
+        PA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        require(p != nullptr, "no device address for the static scratch", PA_EHIP);
+        g_scratch_ptr[device] = static_cast<int32_t*>(p);
+    }
+    return g_scratch_ptr[device];
+}
 
 void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int64_t m, int d, const float* EV,
                                    const uint8_t* EV8, const float* EVscale, const float* EVnorm,

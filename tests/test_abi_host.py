@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
     for name in decl:
         assert hasattr(L, name), name
     assert decl == set(pa.symbols())
-    assert pa.abi_version() == 9
+    assert pa.abi_version() == 10
 
 
 def _csr(rows):
