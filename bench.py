@@ -7,15 +7,18 @@ projection to 64 dims; 25% subgraph (seed + 1-hop expansion); 4,096 pivots in 32
 buckets.  Two forms are measured on the same GPU: reduced vectors stored in
 fp32 and in fp16 (fp32 arithmetic), both followed by fp32 refinement and final
 traversal on the host.  For each form the smallest ef of the sweep reaching
-recall@10 >= 0.95 is found first (untimed), then ``--warmup`` untimed and
-``--steps`` timed searches of all queries run at that ef.  One JSON line goes
-to stdout; progress goes to stderr.
+recall@10 >= 0.95 is found first (untimed), then ``--warmup`` untimed searches and
+three runs of ``--steps`` timed searches of all queries at that ef; ``value`` is the
+median run.  A step starts from the queries in host memory: their upload to the GPU
+is inside it.  One JSON line goes to stdout; progress goes to stderr.
 
 Roofline: the stage-1 traversal kernel is the dominant GPU kernel.  Its
 algorithmic bytes per query are 4*d_r (query) + 4*E (entries) + 4*R per
-expansion (adjacency row) + s*d_r per distance evaluation (gathered reduced
-row, s = bytes per element) + 8*ef (list out), from the kernel's own counters;
-the launch duration comes from HIP events recorded around every launch on the
+expansion (adjacency row) + s*d_r per visited node (gathered reduced row, s =
+bytes per element; |visited| counted in an extra untimed search whose visited
+cache never forgets) + 8*ef (list out); the kernel's own bytes (its distance
+evaluations, re-scores after cache forgets included) are reported beside them.
+The launch duration comes from HIP events recorded around every launch on the
 library's stream during the timed steps.  Peak = 8 TB/s HBM.  ``traffic`` is the
 HBM traffic per launch that rocprofv3's FETCH_SIZE and WRITE_SIZE counters
 measured for the same kernel and configuration, each scaled by what the counter
@@ -38,7 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "beam_kernel_gmm1m_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 BEAM_SOURCES = ("k_beam.hip", "ffloat.hpp", "common.hpp")
 
 
@@ -52,9 +55,10 @@ def beam_source_hash():
 
 
 def measured_traffic(workload, form, ef_gpu):
-    """Counter-measured HBM bytes per beam launch, if the summary matches this kernel and run."""
+    """Counter-measured HBM bytes per beam launch, if the summary for this workload and form
+    (profiles/beam_kernel_<workload>_<form>_traffic.txt) matches this kernel and run."""
     try:
-        with open(TRAFFIC_SUMMARY) as fh:
+        with open(os.path.join(PROFILES, f"beam_kernel_{workload}_{form}_traffic.txt")) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -150,19 +154,22 @@ def sweep(idx, spec, fx, target, efs):
     return (best[1], best[2]), curve
 
 
-def timed(idx, spec, fx, ef, steps, warmup, bloom=False, width=1):
+def timed(idx, spec, fx, ef, steps, warmup, resident=False, **kw):
+    """W untimed and K timed searches of every query at (ef_gpu, ef_cpu).  Each timed step
+    is the whole search from host queries: the upload of the queries to the GPU (pinned
+    staging, host-to-device copy), projection, routing, FES, stage 1, the hand-off and the
+    host stages.  resident=True passes a device copy of the queries made before the timed
+    region instead (no upload inside it), for comparison."""
     import torch
     ef_gpu, ef_cpu = ef
-    # the query batch is resident in HBM (for the GPU stage) and in host memory (for the
-    # host stages) before the timed region; only the stage-1 hand-off crosses PCIe inside it
-    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
+    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous() if resident else None
     for _ in range(warmup):
-        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom, width=width)
+        idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, **kw)
     torch.cuda.synchronize()
     agg = None
     t0 = time.perf_counter()
     for _ in range(steps):
-        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, bloom=bloom, width=width)
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef_gpu, ef_cpu, Q_dev=Qd, **kw)
         if agg is None:
             agg = {k: 0.0 for k in st}
         for k, v in st.items():
@@ -173,16 +180,37 @@ def timed(idx, spec, fx, ef, steps, warmup, bloom=False, width=1):
     return dt, agg, rec
 
 
+def timed_median(idx, spec, fx, ef, steps, warmup, runs=3, **kw):
+    """`runs` timed runs of `steps` searches each (after one warm-up phase); returns the run
+    with the median time (dt, agg, recall) and every run's queries per second."""
+    res = []
+    for i in range(runs):
+        res.append(timed(idx, spec, fx, ef, steps, warmup if i == 0 else 0, **kw))
+    order = sorted(range(runs), key=lambda i: res[i][0])
+    med = res[order[runs // 2]]
+    return med, [round(spec.queries * steps / r[0], 1) for r in res]
+
+
+def visited_per_query(idx, spec, fx, ef, **kw):
+    """|visited| of stage 1 per query (the method's distance evaluations, Algorithm 1 with
+    an exact visited set): counted in one untimed search with the largest visited cache, in
+    which no query forgets a node (checked), so the kernel's count is |visited|.  None if a
+    forget event still happened."""
+    _, _, cnt, _ = idx.search(fx["Q"], spec.k, ef[0], ef[1], cache_log2=13, with_counters=True, **kw)
+    if (cnt[:, 2] != 0).any():
+        return None
+    return float(cnt[:, 1].mean())
+
+
 def cpu_only(idx, spec, fx, target, steps):
     """The library with the GPU stage switched off: plain Algorithm 1 on the full graph on
     the host cores from the FES entries (graceful degradation, section 4.1), the analogue
     of the CPU graph search the paper compares against.  Smallest swept ef reaching the
     target recall, then `steps` timed searches."""
     import torch
-    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
     curve, chosen = [], None
     for ef in sorted(set(spec.ef) | {24, 40, 80, 160}):
-        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef, stage_mask=2, Q_dev=Qd)
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef, stage_mask=2)
         rec = recall(ids, fx["gt"], spec.k)
         curve.append({"ef": ef, "recall": round(rec, 5), "qps": round(fx["Q"].shape[0] / (st["wall_ms"] / 1e3), 1)})
         log(f"  cpu-only ef={ef:4d} recall@{spec.k}={rec:.4f}")
@@ -194,7 +222,7 @@ def cpu_only(idx, spec, fx, target, steps):
     t0 = time.perf_counter()
     agg = 0
     for _ in range(steps):
-        ids, _, cnt, st = idx.search(fx["Q"], spec.k, chosen, chosen, stage_mask=2, Q_dev=Qd, with_counters=True)
+        ids, _, cnt, st = idx.search(fx["Q"], spec.k, chosen, chosen, stage_mask=2, with_counters=True)
         agg += int(cnt[:, 4].sum())
     dt = time.perf_counter() - t0
     return {"value": round(spec.queries * steps / dt, 1), "unit": "queries/s", "ef": chosen,
@@ -203,28 +231,39 @@ def cpu_only(idx, spec, fx, target, steps):
 
 
 def ablation(idx, spec, fx, ef, steps=2):
-    """The pipeline with parts switched off at the chosen (ef_gpu, ef_cpu), in the spirit of
-    the paper's ablation: no refinement (stage 1 candidates go straight to stage 3), no
-    GPU stage (stage 3 alone from the FES entries), and GPU/host overlap across sub-batches
-    (five sub-batches of 2,048 queries) against one launch."""
-    import torch
-    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
-    cases = {"full": {}, "no_refinement": {"stage_mask": 1}, "no_gpu_stage": {"stage_mask": 2},
-             "overlapped_sub_batches_2048": {"batch": 2048}}
-    out = {}
-    for name, kw in cases.items():
-        idx.search(fx["Q"], spec.k, ef[0], ef[1], Q_dev=Qd, **kw)
+    """The paper's ablation (Table 5): components removed one after another, at the chosen
+    (ef_gpu, ef_cpu), all queries in sub-batches of 2,048: the full pipeline (the host
+    stages of a sub-batch overlap the GPU stage of the next ones); without pipelining (the
+    host waits for the GPU stage of every sub-batch); then also without fast entry
+    selection (every query starts from the same predefined pivots); then also without the
+    residual refinement (stage 2); then also without GPU piloting (Algorithm 1 on the full
+    graph on the host from the predefined entries).  Each row reports QPS, recall and the
+    host's full-distance evaluations per query; two single removals are added for
+    reference."""
+    rows = [("full", {"batch": 2048}),
+            ("-pipelining", {"batch": 2048, "serial": True}),
+            ("-pipelining -fes", {"batch": 2048, "serial": True, "fixed_entries": True}),
+            ("-pipelining -fes -refinement", {"batch": 2048, "serial": True, "fixed_entries": True,
+                                              "stage_mask": 1}),
+            ("-pipelining -fes -refinement -gpu_piloting", {"batch": 2048, "serial": True, "fixed_entries": True,
+                                                            "stage_mask": 2}),
+            ("only -fes", {"batch": 2048, "fixed_entries": True}),
+            ("only -refinement", {"batch": 2048, "stage_mask": 1})]
+    out = {"what": "Table 5 rows, cumulative; ef_gpu/ef_cpu fixed at the timed pair; sub-batches of 2,048",
+           "ef_gpu": ef[0], "ef_cpu": ef[1], "rows": {}}
+    for name, kw in rows:
+        idx.search(fx["Q"], spec.k, ef[0], ef[1], **kw)
         t0 = time.perf_counter()
         n2 = n3 = 0
         for _ in range(steps):
-            ids, _, cnt, st = idx.search(fx["Q"], spec.k, ef[0], ef[1], Q_dev=Qd, with_counters=True, **kw)
+            ids, _, cnt, st = idx.search(fx["Q"], spec.k, ef[0], ef[1], with_counters=True, **kw)
             n2 += int(cnt[:, 3].sum())
             n3 += int(cnt[:, 4].sum())
         dt = time.perf_counter() - t0
         m = spec.queries * steps
-        out[name] = {"qps": round(spec.queries * steps / dt, 1), "recall": round(recall(ids, fx["gt"], spec.k), 5),
-                     "host_distances_per_query": round((n2 + n3) / m, 1)}
-        log(f"  ablation {name}: {out[name]}")
+        out["rows"][name] = {"qps": round(m / dt, 1), "recall": round(recall(ids, fx["gt"], spec.k), 5),
+                             "host_distances_per_query": round((n2 + n3) / m, 1)}
+        log(f"  ablation {name}: {out['rows'][name]}")
     return out
 
 
@@ -233,13 +272,12 @@ def top100(idx, spec, fx, target, steps=2):
     import torch
     from synth.knn import exact_knn
     gt100, _ = exact_knn(fx["X"], fx["Q"], 100, spec.metric, device="cuda")
-    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
     curve, best = [], None
     for ef_cpu in (100, 128, 160, 192, 256, 384, 512):
         hit = []
         for ef_gpu in sorted({ef_cpu, min(512, 2 * ef_cpu)}):
-            idx.search(fx["Q"][:1000], 100, ef_gpu, ef_cpu, Q_dev=Qd[:1000])
-            ids, _, _, st = idx.search(fx["Q"], 100, ef_gpu, ef_cpu, Q_dev=Qd)
+            idx.search(fx["Q"][:1000], 100, ef_gpu, ef_cpu)
+            ids, _, _, st = idx.search(fx["Q"], 100, ef_gpu, ef_cpu)
             rec = recall(ids, gt100, 100)
             qps = fx["Q"].shape[0] / (st["wall_ms"] / 1e3)
             curve.append({"ef_gpu": ef_gpu, "ef_cpu": ef_cpu, "recall": round(rec, 5), "qps": round(qps, 1)})
@@ -254,7 +292,7 @@ def top100(idx, spec, fx, target, steps=2):
     _, ef_gpu, ef_cpu = best
     t0 = time.perf_counter()
     for _ in range(steps):
-        ids, _, _, _ = idx.search(fx["Q"], 100, ef_gpu, ef_cpu, Q_dev=Qd)
+        ids, _, _, _ = idx.search(fx["Q"], 100, ef_gpu, ef_cpu)
     dt = time.perf_counter() - t0
     return {"value": round(spec.queries * steps / dt, 1), "unit": "queries/s", "metric": "recall@100",
             "ef_gpu": ef_gpu, "ef_cpu": ef_cpu, "recall": round(recall(ids, gt100, 100), 5), "curve": curve}
@@ -327,19 +365,31 @@ def gemm_leg(spec, fx, V, reps=20):
     return out
 
 
-def roofline(spec, agg, steps, ef, E, xr_bytes, form):
-    """Beam-kernel bytes and time per launch; ef is the stage-1 list size."""
+def roofline(spec, agg, steps, ef, E, xr_bytes, form, visited=None):
+    """Beam-kernel bytes and time per launch; ef is the stage-1 list size.
+
+    Algorithmic bytes per query (the method's own work): 4*d_r (query) + 4*E (entries) +
+    4*R per expansion (adjacency row) + s*d_r per visited node (its reduced row, gathered
+    once: Algorithm 1 scores each visited node once) + 8*ef (list out); |visited| comes
+    from `visited` (per query, counted with a visited cache that never forgets), the
+    expansions from the timed launches' counters.  The kernel's own bytes count its
+    distance evaluations instead, which include the re-scores after visited-cache forget
+    events; both are reported, the fraction is the method's."""
     m = spec.queries * steps
-    algo = (m * (4 * spec.d_r + 4 * E + 8 * ef) + agg["n_exp1"] * 4 * spec.degree
-            + agg["n_dist1"] * xr_bytes * spec.d_r)
+    fixed = m * (4 * spec.d_r + 4 * E + 8 * ef) + agg["n_exp1"] * 4 * spec.degree
+    kernel = fixed + agg["n_dist1"] * xr_bytes * spec.d_r
+    method = fixed + (visited * m if visited is not None else agg["n_dist1"]) * xr_bytes * spec.d_r
     launches = agg["beam_launches"]
-    per_launch_bytes = algo / launches
     avg_ms = agg["beam_ms"] / launches
-    achieved = per_launch_bytes / (avg_ms / 1e3) / 1e9
+    achieved = method / launches / (avg_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(spec.name, form, ef),
-            "kernel": "beam_kernel", "bytes_per_launch": int(per_launch_bytes), "avg_launch_ms": round(avg_ms, 4),
-            "launches": int(launches)}
+            "kernel": "beam_kernel", "bytes_per_launch": int(method / launches),
+            "kernel_bytes_per_launch": int(kernel / launches),
+            "kernel_frac": round(kernel / launches / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "visited_per_query": None if visited is None else round(visited, 2),
+            "distance_evaluations_per_query": round(agg["n_dist1"] / m, 2),
+            "avg_launch_ms": round(avg_ms, 4), "launches": int(launches)}
 
 
 def memory_leg(spec, fx, shared, ef, full_info, steps):
@@ -358,9 +408,9 @@ def memory_leg(spec, fx, shared, ef, full_info, steps):
         idx = build_index(sp, fx, "f16", sh, compact=True)
         dt, agg, rec = timed(idx, sp, fx, ef, steps, 1)
         info = idx.info()
-        # the library's HBM model for the same shape (the timed searches pass q_dev)
+        # the library's HBM model for the same shape (the timed searches upload the queries)
         shape = pa.memory_shape(sp.n, sp.dim, info["R_sub"], sp.n_pivots, sp.r, "f16", queries=sp.queries,
-                                ef_gpu=ef[0], q_on_device=True)
+                                ef_gpu=ef[0])
         out["points"].append({"rho": rho, "hbm_bytes": info["hbm_bytes"],
                               "model_hbm_bytes": pa.hbm_bytes(shape, info["xr_rows"] / sp.n, sp.d_r),
                               "xr_rows": info["xr_rows"],
@@ -371,7 +421,7 @@ def memory_leg(spec, fx, shared, ef, full_info, steps):
     # the planner's choice per HBM budget over the (rho, d_r) grid, at the reconnection
     # degree cap (the subgraph's padded degree is at most that)
     shape = pa.memory_shape(spec.n, spec.dim, spec.degree, spec.n_pivots, spec.r, "f16", queries=spec.queries,
-                            ef_gpu=ef[0], q_on_device=True)
+                            ef_gpu=ef[0])
     rhos, widths = [0.1, 0.25, 0.5, 0.75, 1.0], [32, 64, 128]
     out["plan"] = {"rhos": rhos, "d_r": widths, "choices": []}
     for mb in (32, 64, 128, 256):
@@ -461,10 +511,9 @@ def gpu_only_leg(spec, fx, target, steps):
     pivots = fx["pivot_choice"](np.nonzero(deg > 0)[0], spec.n_pivots, spec.seed)
     idx.build_entries(pivots, fx["kmeans_init_choice"](spec.n_pivots, spec.r, spec.seed), 10)
     log(f"gpu-only index built in {time.time() - t:.1f}s")
-    Qd = torch.as_tensor(fx["Q"]).to("cuda").contiguous()
     curve, chosen = [], None
     for ef in (32, 64, 96, 128, 192, 256, 384, 512):
-        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef, stage_mask=5, Q_dev=Qd)
+        ids, _, _, st = idx.search(fx["Q"], spec.k, ef, ef, stage_mask=5)
         rec = recall(ids, fx["gt"], spec.k)
         curve.append({"ef_gpu": ef, "recall": round(rec, 5), "qps": round(fx["Q"].shape[0] / (st["wall_ms"] / 1e3), 1)})
         log(f"  gpu-only ef={ef:4d} recall@{spec.k}={rec:.4f}")
@@ -477,7 +526,7 @@ def gpu_only_leg(spec, fx, target, steps):
         agg = None
         t0 = time.perf_counter()
         for _ in range(steps):
-            ids, _, _, st = idx.search(fx["Q"], spec.k, chosen, chosen, stage_mask=5, Q_dev=Qd)
+            ids, _, _, st = idx.search(fx["Q"], spec.k, chosen, chosen, stage_mask=5)
             agg = st if agg is None else {k: agg[k] + v for k, v in st.items()}
         dt = time.perf_counter() - t0
         out.update({"value": round(spec.queries * steps / dt, 1), "unit": "queries/s", "ef_gpu": chosen,
@@ -488,29 +537,55 @@ def gpu_only_leg(spec, fx, target, steps):
     return out
 
 
-def cpu_baseline(spec, fx, shared, ef_pair, budget_s):
-    """The oracle's full pipeline, single process, on a bounded sample of queries."""
+def cpu_baseline(spec, fx, shared, ef_pair, budget_s, plain_ef=None):
+    """The oracle, timed on the host cores in worker processes (one per core): the full
+    pipeline (its own fp64 projection, clustering of the same pivots, stages 1-3) at the
+    timed (ef_gpu, ef_cpu), and plain Algorithm 1 on the full graph from the same FES
+    entries at `plain_ef` (the CPU-only leg's ef), each on a bounded sample of queries sized
+    from a short serial calibration so that it takes about budget_s seconds."""
     import oracle
+    from oracle.parallel import host_cores
+    from tests import oracle_jobs
     t = time.time()
     X = fx["X"]
     V, _, _ = oracle.fit_projection(X, spec.d_r, spec.metric)
-    Xr = oracle.project(X, V)
+    V32 = V.astype(np.float32)
+    Xr = oracle.project(X, V32).astype(np.float32)
+    Qr = oracle.project(fx["Q"], V32).astype(np.float32)
     mask, sr, sn = shared["sub"]
     P = Xr[shared["pivots"]]
-    buckets, cent = oracle.balanced_kmeans(P, spec.r, shared["init"])
+    buckets, cent = oracle.balanced_kmeans(P.astype(np.float64), spec.r, shared["init"])
+    cent = cent.astype(np.float32)
     log(f"oracle setup {time.time() - t:.1f}s")
     ef_gpu, ef_cpu = ef_pair
     E = min(ef_gpu, spec.n_pivots // spec.r)
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < spec.queries:
-        oracle.pipeline(fx["Q"][done:done + 1], X, V, fx["rp"], fx["nb"], sr, sn, Xr, cent, buckets, P,
-                        shared["pivots"], k=spec.k, ef_gpu=ef_gpu, ef_cpu=ef_cpu, E=E, metric=spec.metric)
-        done += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(done / dt, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {spec.queries} queries, full pipeline at ef_gpu={ef_gpu} "
-                      f"ef_cpu={ef_cpu}, {dt:.1f}s"}
+    cores = host_cores()
+    arrays = dict(Q=fx["Q"], Qr=Qr, X=X, V=V32, rp=fx["rp"], nb=fx["nb"], sr=sr, sn=sn, Xr=Xr, cent=cent,
+                  buckets=buckets, P=P, pivots=shared["pivots"])
+    out = {"unit": "queries/s", "cores": cores, "kind": "oracle"}
+
+    def leg(kw, label):
+        t0 = time.perf_counter()  # serial calibration on a few queries
+        n_cal = 8
+        oracle.pipeline(fx["Q"][:n_cal], X, V32, fx["rp"], fx["nb"], sr, sn, Xr, cent, buckets, P,
+                        shared["pivots"], Qr=Qr[:n_cal], metric=spec.metric, **kw)
+        rate1 = n_cal / (time.perf_counter() - t0)
+        n = int(min(spec.queries, max(cores * 4, rate1 * cores * budget_s)))
+        rows = np.arange(n)
+        t0 = time.perf_counter()
+        res, = oracle_jobs.pipeline(arrays, [(rows, dict(metric=spec.metric, **kw))], procs=cores, chunk=8)
+        dt = time.perf_counter() - t0
+        rec = recall(res[0], fx["gt"][:n], spec.k)
+        log(f"  oracle {label}: {n} queries on {cores} processes in {dt:.1f}s, recall {rec:.4f}")
+        return {"value": round(n / dt, 2), "sample": f"first {n} of {spec.queries} queries, {label}, {dt:.1f}s "
+                                                     f"on {cores} worker processes", "recall": round(rec, 5)}
+
+    full = leg(dict(k=spec.k, ef_gpu=ef_gpu, ef_cpu=ef_cpu, E=E), f"full pipeline at ef_gpu={ef_gpu} ef_cpu={ef_cpu}")
+    out.update(value=full["value"], sample=full["sample"], recall=full["recall"])
+    if plain_ef is not None:
+        out["plain_algorithm1"] = leg(dict(k=spec.k, ef_gpu=plain_ef, ef_cpu=plain_ef, E=E, use_gpu_stage=False),
+                                      f"Algorithm 1 on the full graph from the FES entries at ef={plain_ef}")
+    return out
 
 
 def serve_bench(idx, spec, fx, rates, seconds, budget):
@@ -571,6 +646,26 @@ def serve_bench(idx, spec, fx, rates, seconds, budget):
     return out
 
 
+def flat_leg(args, spec):
+    """The same shape on a flat mixture (1,024 well separated blobs, centres ~ N(0, 4I)):
+    fixture, fp32 index, the sweep to the target recall (or its end), then one timed run."""
+    fx = build_fixture(spec, "cuda")
+    shared = {}
+    idx = build_index(spec, fx, "f32", shared)
+    ef, curve = sweep(idx, spec, fx, args.target, spec.ef)
+    out = {"workload": f"{spec.name}: N={spec.n} d={spec.dim} {spec.components}-component flat GMM "
+                       f"(centres ~ N(0, 4I)), otherwise as the headline", "curve": curve, "value": None}
+    if ef is not None:
+        dt, agg, rec = timed(idx, spec, fx, ef, max(1, min(args.steps, 5)), 1)
+        out.update(value=round(spec.queries * max(1, min(args.steps, 5)) / dt, 1), unit="queries/s",
+                   ef_gpu=ef[0], ef_cpu=ef[1], recall=round(rec, 5))
+    else:
+        out["note"] = f"recall@{spec.k} stays below {args.target} over the whole ef sweep"
+    idx.close()
+    log(f"  flat mixture: { {k: v for k, v in out.items() if k != 'curve'} }")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -592,6 +687,8 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=32 << 30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy kernel (counter calibration for profiles)")
+    ap.add_argument("--no-flat", dest="flat", action="store_false",
+                    help="skip the flat-mixture leg (the same shape, centres ~ N(0, 4I))")
     ap.add_argument("--ef", default="",
                     help="ef_gpu,ef_cpu to time directly instead of sweeping for the target recall")
     args = ap.parse_args()
@@ -623,14 +720,17 @@ def main():
         if ef is None:
             ef = (spec.ef[-1], spec.ef[-1])
             log(f"  target recall not reached; timing at ef={ef}")
-        dt, agg, rec = timed(idx, spec, fx, ef, args.steps, args.warmup)
+        (dt, agg, rec), runs = timed_median(idx, spec, fx, ef, args.steps, args.warmup)
         E = min(ef[0], spec.n_pivots // spec.r)
         xr_bytes = 4 if form == "f32" else 2
         qps = spec.queries * args.steps / dt
+        visited = visited_per_query(idx, spec, fx, ef)
+        dtr, _, _ = timed(idx, spec, fx, ef, args.steps, 1, resident=True)
         forms[form] = {
             "value": round(qps, 1), "ef_gpu": ef[0], "ef_cpu": ef[1], "recall": round(rec, 5),
-            "ms_per_step": round(dt * 1e3 / args.steps, 3),
-            "roofline": roofline(spec, agg, args.steps, ef[0], E, xr_bytes, form),
+            "ms_per_step": round(dt * 1e3 / args.steps, 3), "runs_qps": runs,
+            "queries_resident_in_hbm_qps": round(spec.queries * args.steps / dtr, 1),
+            "roofline": roofline(spec, agg, args.steps, ef[0], E, xr_bytes, form, visited),
             "gpu_stage": {"beam_ms_per_step": round(agg["beam_ms"] / args.steps, 3),
                           "fes_ms_per_step": round(agg["fes_ms"] / args.steps, 3),
                           "host_wait_ms_per_step": round(agg["host_wait_ms"] / args.steps, 3),
@@ -650,10 +750,12 @@ def main():
             forms[form]["variants"] = {}
             for name, (what, bloom, width) in variants.items():
                 dtb, aggb, recb = timed(idx, spec, fx, ef, args.steps, args.warmup, bloom=bloom, width=width)
+                vis_b = aggb["n_dist1"] / (spec.queries * args.steps) if bloom else \
+                    visited_per_query(idx, spec, fx, ef, width=width)
                 forms[form]["variants"][name] = {
                     "what": what, "value": round(spec.queries * args.steps / dtb, 1), "recall": round(recb, 5),
                     "ms_per_step": round(dtb * 1e3 / args.steps, 3),
-                    "roofline": roofline(spec, aggb, args.steps, ef[0], E, xr_bytes, f"{form}+{name}"),
+                    "roofline": roofline(spec, aggb, args.steps, ef[0], E, xr_bytes, f"{form}+{name}", vis_b),
                     "mean_n_exp1": round(aggb["n_exp1"] / (spec.queries * args.steps), 1),
                     "mean_n_dist1": round(aggb["n_dist1"] / (spec.queries * args.steps), 1)}
                 log(f"{form} {name}: recall={recb:.4f} roofline={forms[form]['variants'][name]['roofline']}")
@@ -680,6 +782,9 @@ def main():
             rates = [float(x) for x in args.serve_rates.split(",") if x]
             serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
         idx.close()
+    if args.flat and not args.no_extra:
+        log("flat mixture (centres ~ N(0, 4I)) at the same shape")
+        extra["flat_mixture"] = flat_leg(args, SPECS[args.workload + "_flat"])
     main_form = "f32" if "f32" in forms else next(iter(forms))
     f = forms[main_form]
     out = {
@@ -712,7 +817,8 @@ def main():
                                       f"{{10,50,100}}, ef in {{64,128,256,512}}, {args.serve_seconds}s per rate, "
                                       f"HBM budget {args.serve_budget} B", "rates": serving}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, fx, shared, (f["ef_gpu"], f["ef_cpu"]), args.cpu_budget)
+        plain_ef = baseline_cpu_only.get("ef") if baseline_cpu_only else f["ef_cpu"]
+        out["cpu_baseline"] = cpu_baseline(spec, fx, shared, (f["ef_gpu"], f["ef_cpu"]), args.cpu_budget, plain_ef)
     print(json.dumps(out), flush=True)
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB

@@ -63,6 +63,8 @@ typedef int32_t pa_status;
 
 #define PA_VISITED_EXACT 0 /* stage-1 visited set: exact (bounded LDS cache that only forgets) */
 #define PA_VISITED_BLOOM 1 /* stage-1 visited set: the paper's lossy Bloom filter in LDS       */
+#define PA_ENTRIES_FES 0   /* entry points: fast entry selection (section 5)                 */
+#define PA_ENTRIES_FIXED 1 /* entry points: predefined nodes, the same for every query      */
 
 #define PA_MAX_EF 512    /* largest candidate-list size of the GPU traversal */
 #define PA_MAX_DEGREE 64 /* largest subgraph out-degree                       */
@@ -215,71 +217,58 @@ pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev,
 
 /* ----------------------------------------------- stage 1: GPU piloting (4.1, Alg. 1) */
 
-/* Batched Algorithm 1 on the subgraph with reduced vectors, one 64-lane wavefront per
- * query.  Qr_dev [m][d_r] fp32 reduced queries; Xr_dev [N][d_r] reduced base vectors of
- * xr_dtype (rows 16-byte aligned: d_r*sizeof % 16 == 0); adj_dev [N][R] (pa_pack_adjacency);
- * entries_dev [m][E] int32 (-1 skipped; ids outside [0, N) are skipped).  Outputs:
- * ids_dev/d_dev [m][ef] - the final candidate list C in (delta, id) order, padded with
- * (-1, +inf); counters_dev [m][4] int32 = (expansions, distance evaluations,
- * visited-cache forget events, guard flag); a forget event is a cache reset or an id that
- * found no free cache slot.  The result equals Algorithm 1 with an exact visited set; the
- * distance-evaluation count equals |visited| when no forget event happened; counters[i][3] is a
- * termination-guard flag (0).  1 <= ef <= PA_MAX_EF,
- * 1 <= R <= PA_MAX_DEGREE.  cache_log2 selects the per-query LDS visited-cache size
- * (2^cache_log2 entries, 8..13; 0 = automatic).  Xr_dev must hold N rows, N <= 2^30.
- * counters_dev[i][3] is 1 if the query stopped at the N-expansion guard (never expected). */
+/* Options of pa_gpu_traverse (NULL: all zero = Algorithm 1 with the exact visited set, an
+ * automatic cache size, one list size for every query). */
+typedef struct {
+    int32_t visited;       /* PA_VISITED_EXACT (Algorithm 1) or PA_VISITED_BLOOM: the
+                              paper's visited filter (section 4.3), see below            */
+    int32_t cache_log2;    /* exact: 2^cache_log2 LDS cache slots per query (8..13);
+                              Bloom: a filter of 32 << cache_log2 bits; 0: automatic
+                              (from ef: the ef_max of a per-query run)                   */
+    int32_t width;         /* entries of C expanded per step: 0 or 1 (Algorithm 1), or 2
+                              (the first two unchecked entries together; needs R <= 32).
+                              Width 2 is not the paper's algorithm: it may expand a node
+                              that Algorithm 1 would have dropped from C first           */
+    const int32_t* ef_dev; /* nullable: per-query list sizes [m] int32 in [1, ef], so
+                              that requests of uneven ef share one launch (the serving
+                              loop): query i keeps ef_dev[i] entries and uses the first
+                              min(E, ef_dev[i]) of its entries; rows keep the stride ef,
+                              padded with (-1, +inf) after ef_dev[i]; with the same
+                              cache_log2 a row equals a run of that query alone with
+                              ef = ef_dev[i]                                               */
+} pa_traverse_opts;
+
+/* Stage 1: batched Algorithm 1 on the subgraph with reduced vectors, one 64-lane
+ * wavefront per query.  Qr_dev [m][d_r] fp32 reduced queries; Xr_dev [N][d_r] reduced base
+ * vectors of xr_dtype (rows 16-byte aligned: d_r*sizeof % 16 == 0, at most 1024 bytes);
+ * adj_dev [N][R] (pa_pack_adjacency); entries_dev [m][E] int32 (-1 skipped; ids outside
+ * [0, N) are skipped).  Outputs: ids_dev/d_dev [m][ef] - the final candidate list C in
+ * (delta, id) order with the correctly rounded fp32 distances, padded with (-1, +inf);
+ * counters_dev [m][4] int32 = (expansions, distance evaluations, visited-cache forget
+ * events, termination-guard flag).  1 <= ef <= PA_MAX_EF, 1 <= R <= PA_MAX_DEGREE,
+ * N <= 2^30.  All device pointers; asynchronous on the stream.
+ *
+ * Exact visited set (default): the per-query LDS cache stores full ids, so it may forget
+ * a visited node (a cache reset, or an id that found no free slot: a forget event) but
+ * never claims an unvisited one; a forgotten node met again is re-scored and dropped, so
+ * the result equals Algorithm 1 with an exact visited set, and the distance-evaluation
+ * count equals |visited| when no forget event happened (it exceeds it by the re-scores
+ * otherwise).  The guard flag is 1 only if a query stopped at the N-expansion guard
+ * (never expected).
+ *
+ * Bloom visited filter (visited = PA_VISITED_BLOOM): each query tracks visited nodes in
+ * a Bloom filter in LDS with two hashes, bit_i(v) = ((uint32)v * A_i mod 2^32) >>
+ * (32 - log2 bits), A_1 = 0x9E3779B1, A_2 = 0x85EBCA77.  A node whose two bits are set
+ * counts as visited, also when other nodes set them (a false positive: it is never scored
+ * here).  The ids of one adjacency row (and each group of 64 entries) are all tested
+ * against the filter as it was before the group, then their bits are set; an id that
+ * appears twice in a group is scored twice and listed once.  Counters as above with
+ * counters[i][2] = 0. */
 pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
                           int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
                           const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
-                          int32_t cache_log2, int32_t* ids_dev, float* d_dev,
+                          const pa_traverse_opts* opts, int32_t* ids_dev, float* d_dev,
                           int32_t* counters_dev, void* stream);
-
-/* Stage 1 with the paper's visited filter (section 4.3): as pa_gpu_traverse, except that
- * each query tracks visited nodes in a Bloom filter of 2^filter_log2 bits in LDS
- * (13..18; 0 = automatic, the same bytes as the automatic exact cache) with two hashes,
- * bit_i(v) = ((uint32)v * A_i mod 2^32) >> (32 - filter_log2), A_1 = 0x9E3779B1,
- * A_2 = 0x85EBCA77.  A node whose two bits are set counts as visited, also when other
- * nodes set them (a false positive: it is never scored here).  The ids of one adjacency
- * row (and each group of 64 entries) are all tested against the filter as it was before
- * the group, then their bits are set; an id that appears twice in a group is scored twice
- * and listed once.  The result is Algorithm 1 with this visited rule; counters as for
- * pa_gpu_traverse with counters[i][2] = 0. */
-pa_status pa_gpu_traverse_bloom(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
-                                int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
-                                const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
-                                int32_t filter_log2, int32_t* ids_dev, float* d_dev,
-                                int32_t* counters_dev, void* stream);
-
-/* Options of pa_gpu_traverse_ex. */
-typedef struct {
-    int32_t visited;     /* PA_VISITED_EXACT or PA_VISITED_BLOOM                        */
-    int32_t cache_log2;  /* exact: 2^cache_log2 cache slots (8..13); Bloom: a filter of
-                            32 << cache_log2 bits; 0: automatic                          */
-    int32_t width;       /* entries of C expanded per step: 1 (Algorithm 1), or 2 (the
-                            first two unchecked entries together; needs R <= 32).  Width
-                            2 is not the paper's algorithm: it may expand a node that
-                            Algorithm 1 would have dropped from C first                 */
-} pa_traverse_opts;
-
-/* Stage 1 with options (opts NULL: exact, automatic, width 1 = pa_gpu_traverse).  As
- * pa_gpu_traverse otherwise; with the Bloom filter as pa_gpu_traverse_bloom. */
-pa_status pa_gpu_traverse_ex(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
-                             int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
-                             const int32_t* entries_dev, int32_t E, int32_t ef, int32_t metric,
-                             const pa_traverse_opts* opts, int32_t* ids_dev, float* d_dev,
-                             int32_t* counters_dev, void* stream);
-
-/* Stage 1 with a list size per query, so that requests of uneven ef share one launch
- * (used by the serving loop).  As pa_gpu_traverse, plus ef_dev [m] int32 with
- * 1 <= ef_dev[i] <= ef_max: query i keeps a list of ef_dev[i] entries and uses the first
- * min(E, ef_dev[i]) of its entries.  Output rows keep the stride ef_max; row i holds its
- * ef_dev[i] entries followed by (-1, +inf).  Each row equals what pa_gpu_traverse returns
- * for that query alone with ef = ef_dev[i] and E = min(E, ef_dev[i]). */
-pa_status pa_gpu_traverse_ragged(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev,
-                                 int32_t xr_dtype, int64_t N, const int32_t* adj_dev, int32_t R,
-                                 const int32_t* entries_dev, int32_t E, const int32_t* ef_dev,
-                                 int32_t ef_max, int32_t metric, int32_t* ids_dev, float* d_dev,
-                                 int32_t* counters_dev, void* stream);
 
 /* ------------------------------------------- stages 2 and 3 on the host (4.1) */
 
@@ -494,6 +483,15 @@ typedef struct {
                              32 << cache_log2 bits)                                 */
     int32_t width;        /* stage-1 expansion width (0 or 1: Algorithm 1; 2: see
                              pa_traverse_opts)                                       */
+    int32_t entries;      /* PA_ENTRIES_FES (0), or PA_ENTRIES_FIXED: no entry
+                             selection; every query starts from the same E pivots,
+                             taken one per bucket in turn (pivot j of bucket c for
+                             entry e = j * r + c), the "predefined nodes" start of
+                             section 5 (the ablation of Table 5)                      */
+    int32_t serial;       /* 0: the host stages of sub-batch b overlap the GPU stage
+                             of the later ones (pipelining, section 4.1); 1: the host
+                             stages start after the GPU stage of every sub-batch
+                             (the ablation of Table 5)                               */
 } pa_search_opts;
 
 typedef struct {

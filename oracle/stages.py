@@ -71,7 +71,7 @@ def _order_gap(keys) -> float:
 def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets, pivot_vecs,
              pivot_ids, *, k: int, ef_gpu: int, ef_cpu: int, E: int, metric: str = "l2",
              refine_steps: int = 2, use_gpu_stage: bool = True, use_refine: bool = True, bloom_log2=None,
-             use_final: bool = True, width: int = 1, Qr=None, with_margin: bool = False):
+             use_final: bool = True, width: int = 1, Qr=None, with_margin: bool = False, fixed_entries=None):
     """All stages for every query; returns (ids [m][k], dists [m][k], counters [m][4]).
 
     counters = (stage-1 distances, stage-2 distances, stage-3 distances, stage-3 steps).
@@ -86,13 +86,21 @@ def pipeline(Q, X, V, rowptr, nbrs, sub_rowptr, sub_nbrs, Xr, centroids, buckets
     with_margin=True appends margin [m]: per query, the smallest relative gap over every
     comparison that decided its result (routing, the entry cut, each stage's Algorithm 1
     decisions, and the order of the k returned keys).
+
+    fixed_entries: node ids every query starts from instead of the entries fast entry
+    selection picks (the predefined entry points section 5 contrasts FES with; the
+    ablation without FES); no routing or entry cut is decided then.
     """
     if not use_final and not use_gpu_stage:
         raise ValueError("without the GPU stage the final traversal must run")
     Q = np.asarray(Q, dtype=np.float64)
     Qr = as_f32(project(Q, V)) if Qr is None else np.asarray(Qr, dtype=np.float64)
-    entries, _, _, e_margin = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
     m = Q.shape[0]
+    if fixed_entries is None:
+        entries, _, _, e_margin = select_entries(Qr, centroids, buckets, pivot_vecs, pivot_ids, E, metric)
+    else:
+        entries = np.tile(np.asarray(fixed_entries, dtype=np.int64)[None, :], (m, 1))
+        e_margin = np.full(m, np.inf)
     out_i = np.full((m, k), -1, dtype=np.int64)
     out_d = np.full((m, k), np.inf)
     counters = np.zeros((m, 4), dtype=np.int64)

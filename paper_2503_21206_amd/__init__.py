@@ -23,6 +23,7 @@ PA_METRIC_L2, PA_METRIC_IP = 0, 1
 PA_F32, PA_F16, PA_BF16, PA_FP8E4M3 = 0, 1, 2, 3
 PA_SAMPLE_UNIFORM, PA_SAMPLE_SEED_EXPAND = 0, 1
 PA_VISITED_EXACT, PA_VISITED_BLOOM = 0, 1
+PA_ENTRIES_FES, PA_ENTRIES_FIXED = 0, 1
 PA_MAX_EF = 512
 
 METRICS = {"l2": PA_METRIC_L2, "ip": PA_METRIC_IP}
@@ -45,11 +46,12 @@ class Params(C.Structure):
 class SearchOpts(C.Structure):
     _fields_ = [("ef_gpu", C.c_int32), ("ef_cpu", C.c_int32), ("E", C.c_int32), ("batch", C.c_int32),
                 ("stage_mask", C.c_int32), ("cache_log2", C.c_int32), ("threads", C.c_int32),
-                ("handoff", C.c_int32), ("q_dev", C.c_void_p), ("visited", C.c_int32), ("width", C.c_int32)]
+                ("handoff", C.c_int32), ("q_dev", C.c_void_p), ("visited", C.c_int32), ("width", C.c_int32),
+                ("entries", C.c_int32), ("serial", C.c_int32)]
 
 
 class TraverseOpts(C.Structure):
-    _fields_ = [("visited", C.c_int32), ("cache_log2", C.c_int32), ("width", C.c_int32)]
+    _fields_ = [("visited", C.c_int32), ("cache_log2", C.c_int32), ("width", C.c_int32), ("ef_dev", C.c_void_p)]
 
 
 class SearchStats(C.Structure):
@@ -102,10 +104,8 @@ _SIGS = {
     "pa_build_entries": [_P, _I32, _I32, _I32, _P, _I32, _P, _P],
     "pa_select_entries": [_P, _P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P],
     "pa_select_entries_noalloc": [_P, _P, _I64, _I32, _P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P],
-    "pa_gpu_traverse": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P],
-    "pa_gpu_traverse_bloom": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _I32, _P, _P, _P,
-                              _P],
-    "pa_gpu_traverse_ex": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, _P, _P, _P, _P, _P],
+    "pa_gpu_traverse": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _I32, _I32, C.POINTER(TraverseOpts), _P,
+                        _P, _P, _P],
     "pa_cpu_stages": [_P, _I64, _I32, _P, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _I32,
                       _P, _P, _P],
     "pa_cpu_search": [_P, _I64, _I32, _P, _I32, _P, _I64, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P],
@@ -126,7 +126,6 @@ _SIGS = {
     "pa_search": [_P, _P, _I64, _I32, C.POINTER(SearchOpts), _P, _P, _P, C.POINTER(SearchStats)],
     "pa_quantize_fp8_rows": [_P, _I64, _I32, _P, _P],
     "pa_select_entries_fp8": [_P, _P, _I64, _I32, _P, _P, _P, _P, _P, _I32, _I32, _I32, _I32, _I32, _P, _P, _P],
-    "pa_gpu_traverse_ragged": [_P, _I64, _I32, _P, _I32, _I64, _P, _I32, _P, _I32, _P, _I32, _I32, _P, _P, _P, _P],
     "pa_server_create": [_P, C.POINTER(ServerParams), C.POINTER(_P)],
     "pa_server_submit": [_P, _P, _I32, _I32, C.c_uint64],
     "pa_server_poll": [_P, _I32, C.POINTER(ResultInfo), _P, _P, C.POINTER(_I32)],
@@ -373,10 +372,11 @@ def select_entries_fp8(Qr, cluster, EV, EV8, EVscale, EVnorm, EVid, E: int, K: i
 
 
 def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: int = 0, stream=None,
-                 bloom_log2: int = -1, width: int = 1):
+                 bloom_log2: int = -1, width: int = 1, efs=None):
     """Stage 1 on device tensors -> (ids [m][ef] int32, dists [m][ef] fp32, counters [m][4] int32).
     bloom_log2 >= 0 selects the Bloom-filter visited set of 2^bloom_log2 bits (0: automatic);
-    width 2 expands the first two unchecked entries per step (pa_gpu_traverse_ex)."""
+    width 2 expands the first two unchecked entries per step; efs [m] (device int32): a list
+    size per query, with ef the largest (pa_gpu_traverse)."""
     import torch
     m, d_r = Qr.shape
     N, R = adj.shape
@@ -385,43 +385,33 @@ def gpu_traverse(Qr, Xr, adj, entries, ef: int, metric: str = "l2", cache_log2: 
         raise ValueError(f"Xr must be [{N}][{d_r}] to match adj and Qr, got {tuple(Xr.shape)}")
     if entries.dim() != 2 or entries.shape[0] != m:
         raise ValueError("entries must be [m][E]")
+    if efs is not None and tuple(efs.shape) != (m,):
+        raise ValueError("efs must be [m]")
     E = entries.shape[1]
     ids = torch.empty((m, ef), dtype=torch.int32, device=Qr.device)
     dist = torch.empty((m, ef), dtype=torch.float32, device=Qr.device)
     cnt = torch.empty((m, 4), dtype=torch.int32, device=Qr.device)
-    if width != 1:
-        cl = cache_log2 if bloom_log2 < 0 else (0 if bloom_log2 == 0 else bloom_log2 - 5)
-        opts = TraverseOpts(PA_VISITED_EXACT if bloom_log2 < 0 else PA_VISITED_BLOOM, cl, width)
-        _check(lib().pa_gpu_traverse_ex(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
-                                        _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E,
-                                        ef, METRICS[metric], C.byref(opts), _dev(ids), _dev(dist), _dev(cnt),
-                                        _stream(stream)))
-        return ids, dist, cnt
-    fn = lib().pa_gpu_traverse if bloom_log2 < 0 else lib().pa_gpu_traverse_bloom
-    _check(fn(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
-              _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E, ef,
-              METRICS[metric], cache_log2 if bloom_log2 < 0 else bloom_log2, _dev(ids), _dev(dist), _dev(cnt),
-              _stream(stream)))
+    if bloom_log2 < 0:
+        opts = TraverseOpts(PA_VISITED_EXACT, cache_log2, width, None)
+    else:
+        opts = TraverseOpts(PA_VISITED_BLOOM, 0 if bloom_log2 == 0 else bloom_log2 - 5, width, None)
+        if bloom_log2 != 0 and not 13 <= bloom_log2 <= 18:
+            raise PilotannError(-1, "bloom_log2 must be 0 or 13..18")
+    if efs is not None:
+        opts.ef_dev = _dev(efs, torch.int32, "efs")
+    _check(lib().pa_gpu_traverse(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
+                                 _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"), E, ef,
+                                 METRICS[metric], C.byref(opts), _dev(ids), _dev(dist), _dev(cnt), _stream(stream)))
     return ids, dist, cnt
 
 
-def gpu_traverse_ragged(Qr, Xr, adj, entries, efs, metric: str = "l2", stream=None):
+def gpu_traverse_ragged(Qr, Xr, adj, entries, efs, metric: str = "l2", stream=None, **kw):
     """Stage 1 with a per-query list size efs [m] (device int32) -> rows of stride max(efs)."""
-    import torch
-    m, d_r = Qr.shape
-    N, R = adj.shape
-    dt = {torch.float32: PA_F32, torch.float16: PA_F16, torch.bfloat16: PA_BF16}[Xr.dtype]
-    if tuple(Xr.shape) != (N, d_r) or entries.dim() != 2 or entries.shape[0] != m or tuple(efs.shape) != (m,):
-        raise ValueError("Xr [N][d_r], entries [m][E] and efs [m] must match Qr and adj")
+    m = Qr.shape[0]
+    if tuple(efs.shape) != (m,):
+        raise ValueError("efs must be [m]")
     ef_max = int(efs.max().item()) if m else 1
-    ids = torch.empty((m, ef_max), dtype=torch.int32, device=Qr.device)
-    dist = torch.empty((m, ef_max), dtype=torch.float32, device=Qr.device)
-    cnt = torch.empty((m, 4), dtype=torch.int32, device=Qr.device)
-    _check(lib().pa_gpu_traverse_ragged(_dev(Qr, torch.float32, "Qr"), m, d_r, _dev(Xr, name="Xr"), dt, N,
-                                        _dev(adj, torch.int32, "adj"), R, _dev(entries, torch.int32, "entries"),
-                                        entries.shape[1], _dev(efs, torch.int32, "efs"), ef_max, METRICS[metric],
-                                        _dev(ids), _dev(dist), _dev(cnt), _stream(stream)))
-    return ids, dist, cnt
+    return gpu_traverse(Qr, Xr, adj, entries, ef_max, metric, stream=stream, efs=efs, **kw)
 
 
 def cpu_stages(X, sub_adj, full_adj, Q, beam, ef_cpu: int, k: int, refine_steps: int = 2,
@@ -600,11 +590,14 @@ class Index:
 
     def search(self, Q, k: int, ef_gpu: int, ef_cpu: int = 0, E: int = 0, batch: int = 0, stage_mask: int = 0,
                cache_log2: int = 0, threads: int = 0, with_counters: bool = False, handoff: int = 0,
-               Q_dev=None, bloom: bool = False, width: int = 1):
+               Q_dev=None, bloom: bool = False, width: int = 1, fixed_entries: bool = False,
+               serial: bool = False):
         """Q_dev: optional torch tensor on the index's device holding the same [m][dim] fp32
         queries as Q; the GPU stage then reads them from HBM instead of uploading Q.
         bloom: stage 1 tracks visited nodes in the paper's Bloom filter (32 << cache_log2
-        bits) instead of the exact set.  width 2: stage 1 expands two entries per step."""
+        bits) instead of the exact set.  width 2: stage 1 expands two entries per step.
+        fixed_entries: no entry selection, the same predefined pivots for every query.
+        serial: the host stages wait for the GPU stage of every sub-batch (no pipelining)."""
         Q, pq = _host(Q, np.float32)
         m = Q.shape[0]
         if Q.ndim != 2 or Q.shape[1] != self.cfg.dim:
@@ -621,7 +614,7 @@ class Index:
         dist = np.empty((m, k), dtype=np.float32)
         cnt = np.empty((m, 8), dtype=np.int32) if with_counters else None
         opts = SearchOpts(ef_gpu, ef_cpu, E, batch, stage_mask, cache_log2, threads, handoff, qd, 1 if bloom else 0,
-                          width)
+                          width, 1 if fixed_entries else 0, 1 if serial else 0)
         st = SearchStats()
         _check(lib().pa_search(self._h, pq, m, k, C.byref(opts), ids.ctypes.data_as(_P), dist.ctypes.data_as(_P),
                                cnt.ctypes.data_as(_P) if cnt is not None else None, C.byref(st)))

@@ -291,7 +291,7 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pa_abi_version(void) { return 10; }
+int32_t pa_abi_version(void) { return 11; }
 
 pa_status pa_device_init(int32_t device) {
     return guarded([&] {
@@ -482,58 +482,10 @@ pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev,
 
 pa_status pa_gpu_traverse(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev, int32_t xr_dtype, int64_t N,
                           const int32_t* adj_dev, int32_t R, const int32_t* entries_dev, int32_t E, int32_t ef,
-                          int32_t metric, int32_t cache_log2, int32_t* ids_dev, float* d_dev, int32_t* counters_dev,
-                          void* stream) {
+                          int32_t metric, const pa_traverse_opts* opts, int32_t* ids_dev, float* d_dev,
+                          int32_t* counters_dev, void* stream) {
     return guarded([&] {
-        require(m >= 0 && N >= 0 && N < (int64_t{1} << 31), "need m >= 0 and 0 <= N < 2^31");
-        require(ef >= 1 && ef <= PA_MAX_EF, "ef must be in [1, 512]");
-        require(R >= 1 && R <= PA_MAX_DEGREE, "R must be in [1, 64]");
-        require(E >= 0, "E must be >= 0");
-        require(d_r > 0 && d_r <= PA_MAX_DR, "d_r must be in [1, 256]");
-        require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
-        const size_t row = static_cast<size_t>(d_r) * dtype_size(xr_dtype);
-        require(row % 16 == 0 && row <= 1024, "reduced rows must be a multiple of 16 bytes (at most 1024)");
-        require(cache_log2 == 0 || (cache_log2 >= 8 && cache_log2 <= 13), "cache_log2 must be 0 or 8..13");
-        if (cache_log2 != 0) require((1 << cache_log2) >= 4 * ((ef + 63) / 64 * 64), "visited cache must hold 4*ef ids");
-        if (m == 0) return;
-        require(Qr_dev && Xr_dev && adj_dev && ids_dev && d_dev && counters_dev && (entries_dev || E == 0),
-                "null pointer");
-        launch_beam(Qr_dev, m, d_r, Xr_dev, xr_dtype, N, adj_dev, R, entries_dev, E, ef, metric, cache_log2, ids_dev,
-                    d_dev, counters_dev, as_stream(stream));
-    });
-}
-
-pa_status pa_gpu_traverse_bloom(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev, int32_t xr_dtype,
-                                int64_t N, const int32_t* adj_dev, int32_t R, const int32_t* entries_dev, int32_t E,
-                                int32_t ef, int32_t metric, int32_t filter_log2, int32_t* ids_dev, float* d_dev,
-                                int32_t* counters_dev, void* stream) {
-    return guarded([&] {
-        require(m >= 0 && N >= 0 && N < (int64_t{1} << 31), "need m >= 0 and 0 <= N < 2^31");
-        require(ef >= 1 && ef <= PA_MAX_EF, "ef must be in [1, 512]");
-        require(R >= 1 && R <= PA_MAX_DEGREE, "R must be in [1, 64]");
-        require(E >= 0, "E must be >= 0");
-        require(d_r > 0 && d_r <= PA_MAX_DR, "d_r must be in [1, 256]");
-        require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
-        const size_t row = static_cast<size_t>(d_r) * dtype_size(xr_dtype);
-        require(row % 16 == 0 && row <= 1024, "reduced rows must be a multiple of 16 bytes (at most 1024)");
-        require(filter_log2 == 0 || (filter_log2 >= 13 && filter_log2 <= 18), "filter_log2 must be 0 or 13..18");
-        const int cache_log2 = filter_log2 == 0 ? 0 : filter_log2 - 5;
-        if (cache_log2 != 0)
-            require((1 << cache_log2) >= 4 * ((ef + 63) / 64 * 64), "the filter must have at least 128*ef bits");
-        if (m == 0) return;
-        require(Qr_dev && Xr_dev && adj_dev && ids_dev && d_dev && counters_dev && (entries_dev || E == 0),
-                "null pointer");
-        launch_beam(Qr_dev, m, d_r, Xr_dev, xr_dtype, N, adj_dev, R, entries_dev, E, ef, metric, cache_log2, ids_dev,
-                    d_dev, counters_dev, as_stream(stream), nullptr, PA_VISITED_BLOOM);
-    });
-}
-
-pa_status pa_gpu_traverse_ex(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev, int32_t xr_dtype,
-                             int64_t N, const int32_t* adj_dev, int32_t R, const int32_t* entries_dev, int32_t E,
-                             int32_t ef, int32_t metric, const pa_traverse_opts* opts, int32_t* ids_dev,
-                             float* d_dev, int32_t* counters_dev, void* stream) {
-    return guarded([&] {
-        const pa_traverse_opts o = opts ? *opts : pa_traverse_opts{PA_VISITED_EXACT, 0, 1};
+        const pa_traverse_opts o = opts ? *opts : pa_traverse_opts{PA_VISITED_EXACT, 0, 1, nullptr};
         require(m >= 0 && N >= 0 && N < (int64_t{1} << 31), "need m >= 0 and 0 <= N < 2^31");
         require(ef >= 1 && ef <= PA_MAX_EF, "ef must be in [1, 512]");
         require(R >= 1 && R <= PA_MAX_DEGREE, "R must be in [1, 64]");
@@ -541,38 +493,19 @@ pa_status pa_gpu_traverse_ex(const float* Qr_dev, int64_t m, int32_t d_r, const 
         require(d_r > 0 && d_r <= PA_MAX_DR, "d_r must be in [1, 256]");
         require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
         require(o.visited == PA_VISITED_EXACT || o.visited == PA_VISITED_BLOOM, "visited must be exact or bloom");
-        require(o.width == 1 || (o.width == 2 && R <= 32), "width must be 1, or 2 with R <= 32");
+        require(o.width == 0 || o.width == 1 || (o.width == 2 && R <= 32), "width must be 1, or 2 with R <= 32");
         const size_t row = static_cast<size_t>(d_r) * dtype_size(xr_dtype);
         require(row % 16 == 0 && row <= 1024, "reduced rows must be a multiple of 16 bytes (at most 1024)");
         require(o.cache_log2 == 0 || (o.cache_log2 >= 8 && o.cache_log2 <= 13), "cache_log2 must be 0 or 8..13");
         if (o.cache_log2 != 0)
-            require((1 << o.cache_log2) >= 4 * ((ef + 63) / 64 * 64), "the visited cache must hold 4*ef ids");
+            require((1 << o.cache_log2) >= 4 * ((ef + 63) / 64 * 64),
+                    o.visited == PA_VISITED_BLOOM ? "the Bloom filter must have at least 128*ef bits"
+                                                  : "the visited cache must hold 4*ef ids");
         if (m == 0) return;
         require(Qr_dev && Xr_dev && adj_dev && ids_dev && d_dev && counters_dev && (entries_dev || E == 0),
                 "null pointer");
         launch_beam(Qr_dev, m, d_r, Xr_dev, xr_dtype, N, adj_dev, R, entries_dev, E, ef, metric, o.cache_log2, ids_dev,
-                    d_dev, counters_dev, as_stream(stream), nullptr, o.visited, nullptr, true, o.width);
-    });
-}
-
-pa_status pa_gpu_traverse_ragged(const float* Qr_dev, int64_t m, int32_t d_r, const void* Xr_dev, int32_t xr_dtype,
-                                 int64_t N, const int32_t* adj_dev, int32_t R, const int32_t* entries_dev, int32_t E,
-                                 const int32_t* ef_dev, int32_t ef_max, int32_t metric, int32_t* ids_dev, float* d_dev,
-                                 int32_t* counters_dev, void* stream) {
-    return guarded([&] {
-        require(m >= 0 && N >= 0 && N < (int64_t{1} << 31), "need m >= 0 and 0 <= N < 2^31");
-        require(ef_max >= 1 && ef_max <= PA_MAX_EF, "ef_max must be in [1, 512]");
-        require(R >= 1 && R <= PA_MAX_DEGREE, "R must be in [1, 64]");
-        require(E >= 0, "E must be >= 0");
-        require(d_r > 0 && d_r <= PA_MAX_DR, "d_r must be in [1, 256]");
-        require(metric == PA_METRIC_L2 || metric == PA_METRIC_IP, "unknown metric");
-        const size_t row = static_cast<size_t>(d_r) * dtype_size(xr_dtype);
-        require(row % 16 == 0 && row <= 1024, "reduced rows must be a multiple of 16 bytes (at most 1024)");
-        if (m == 0) return;
-        require(Qr_dev && Xr_dev && adj_dev && ef_dev && ids_dev && d_dev && counters_dev && (entries_dev || E == 0),
-                "null pointer");
-        launch_beam(Qr_dev, m, d_r, Xr_dev, xr_dtype, N, adj_dev, R, entries_dev, E, ef_max, metric, 0, ids_dev, d_dev,
-                    counters_dev, as_stream(stream), ef_dev);
+                    d_dev, counters_dev, as_stream(stream), o.ef_dev, o.visited, nullptr, true, o.width <= 1 ? 1 : 2);
     });
 }
 

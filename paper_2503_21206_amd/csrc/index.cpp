@@ -195,6 +195,10 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     require(k >= 1 && m >= 0, "need k >= 1 and m >= 0");
     const int E = o.E > 0 ? o.E : std::min(o.ef_gpu, idx->n_b);
     require(E >= 1 && E <= PA_MAX_EF, "E must be in [1, 512]");
+    require(o.entries == PA_ENTRIES_FES || o.entries == PA_ENTRIES_FIXED, "entries must be FES (0) or fixed (1)");
+    const bool fixed_entries = o.entries == PA_ENTRIES_FIXED;
+    require(!fixed_entries || E <= idx->n_b * idx->p.r, "fixed entries: E must not exceed the pivot count");
+    require(o.serial == 0 || o.serial == 1, "serial must be 0 or 1");
     require(o.visited == PA_VISITED_EXACT || o.visited == PA_VISITED_BLOOM, "visited must be exact (0) or bloom (1)");
     const int width = o.width <= 1 ? 1 : o.width;
     require(width == 1 || (width == 2 && idx->R_sub <= 32), "width must be 0, 1, or 2 with a subgraph degree <= 32");
@@ -249,6 +253,13 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     auto* ent_pin = static_cast<int32_t*>(idx->p_ent.ensure(sizeof(int32_t) * m * E));
     ensure_events(idx, static_cast<size_t>(4 * nbatch));
     hipStream_t s = idx->stream;
+    if (fixed_entries) {  // the same predefined pivots for every query, one per bucket in turn (device ids)
+        const int r_ = idx->p.r, n_b = idx->n_b;
+        std::vector<int32_t> fixed(static_cast<size_t>(E));
+        for (int e = 0; e < E; ++e)
+            fixed[e] = index_device_id(idx, idx->bucket_ids[static_cast<size_t>(e % r_) * n_b + e / r_]);
+        for (int64_t i = 0; i < m; ++i) std::memcpy(ent_pin + i * E, fixed.data(), sizeof(int32_t) * E);
+    }
 
     // enqueue every batch's GPU work; the host consumes them in order below
     for (int64_t b = 0; b < nbatch; ++b) {
@@ -261,7 +272,14 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
         PA_HIP(hipEventRecord(ev[0], s));
         launch_project(q_src + b0 * D, nb, D, static_cast<const float*>(idx->V_dev.p), d_r, qr_dev + b0 * d_r, PA_F32,
                        static_cast<const float*>(idx->cent_dev.p), r, cl_dev + b0, s);
-        index_select_entries(idx, qr_dev + b0 * d_r, cl_dev + b0, nb, E, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev, s);
+        if (fixed_entries) {
+            if (gpu_stage)
+                PA_HIP(hipMemcpyAsync(eid_dev + b0 * E, ent_pin + b0 * E, sizeof(int32_t) * nb * E,
+                                      hipMemcpyHostToDevice, s));
+        } else {
+            index_select_entries(idx, qr_dev + b0 * d_r, cl_dev + b0, nb, E, eid_dev + b0 * E, ed_dev + b0 * E, scr_dev,
+                                 s);
+        }
         PA_HIP(hipEventRecord(ev[1], s));
         if (gpu_stage) {
             launch_beam(qr_dev + b0 * d_r, nb, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
@@ -275,8 +293,9 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
                                   s));
         } else {
             PA_HIP(hipEventRecord(ev[2], s));
-            PA_HIP(hipMemcpyAsync(ent_pin + b0 * E, eid_dev + b0 * E, sizeof(int32_t) * nb * E, hipMemcpyDeviceToHost,
-                                  s));
+            if (!fixed_entries)  // fixed entries are in ent_pin already
+                PA_HIP(hipMemcpyAsync(ent_pin + b0 * E, eid_dev + b0 * E, sizeof(int32_t) * nb * E,
+                                      hipMemcpyDeviceToHost, s));
         }
         PA_HIP(hipEventRecord(ev[3], s));
     }
@@ -290,7 +309,9 @@ void search(pa_index* idx, const float* Q, int64_t m, int k, const pa_search_opt
     for (int64_t b = 0; b < nbatch; ++b) {
         const int64_t b0 = starts[b], nb = starts[b + 1] - starts[b];
         const auto w0 = std::chrono::steady_clock::now();
-        PA_HIP(hipEventSynchronize(idx->events[static_cast<size_t>(4 * b + 3)]));
+        // pipelined: sub-batch b as soon as its GPU stage is done; serial: after the last one
+        const int64_t wait_for = o.serial ? nbatch - 1 : b;
+        PA_HIP(hipEventSynchronize(idx->events[static_cast<size_t>(4 * wait_for + 3)]));
         wait_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
         idx->pool->parallel_for(nb, [&](int64_t j, int w) {
             const int64_t i = b0 + j;

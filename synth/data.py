@@ -75,6 +75,11 @@ SPECS = {
         sample_mode="seed_expand", n_pivots=4096,
         ef=(32, 48, 64, 96, 128, 192, 256, 384, 512), xr_dtypes=("f32", "f16"),
         kind="hgmm", levels=(8, 8, 16), spreads=(2.0, 1.0, 0.5)),
+    "gmm1m_flat": WorkloadSpec(
+        name="gmm1m_flat", config=2, n=1_000_000, dim=128, components=1024,
+        queries=10_000, metric="l2", k=10, degree=32, d_r=64, rho=0.25,
+        sample_mode="seed_expand", n_pivots=4096,
+        ef=(32, 48, 64, 96, 128, 192, 256, 384, 512), xr_dtypes=("f32", "f16"), kind="gmm"),
     "aniso10m": WorkloadSpec(
         name="aniso10m", config=3, n=10_000_000, dim=768, components=1024,
         queries=10_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
     for name in decl:
         assert hasattr(L, name), name
     assert decl == set(pa.symbols())
-    assert pa.abi_version() == 10
+    assert pa.abi_version() == 11
 
 
 def _csr(rows):
@@ -331,3 +331,9 @@ def test_bench_roofline_counts_the_algorithmic_bytes():
     assert r["bytes_per_launch"] == (20480 + 83200 + 2219520) // 2
     assert abs(r["achieved"] - 2323200 / 2 / 0.5e-3 / 1e9) < 0.05
     assert r["peak"] == 8000.0 and r["traffic"] is None  # no profile for this workload
+    # with |visited| counted separately (766 per query instead of the kernel's 867 evaluations,
+    # which include re-scores after forget events) the method's bytes use |visited|
+    r = bench.roofline(spec, agg, 2, 64, 64, 4, "f32", visited=766.0)
+    method = 20480 + 83200 + 20 * 766 * 256
+    assert r["bytes_per_launch"] == method // 2 and r["kernel_bytes_per_launch"] == (20480 + 83200 + 2219520) // 2
+    assert abs(r["frac"] - method / 2 / 0.5e-3 / 1e9 / 8000.0) < 1e-4

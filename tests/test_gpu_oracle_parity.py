@@ -139,7 +139,19 @@ SEARCH_FORMS = [
     ("width2", dict(width=2), dict(width=2), 1000),
     ("stage1_no_refine", dict(stage_mask=1), dict(use_refine=False), 1000),
     ("no_gpu_stage", dict(stage_mask=2), dict(use_gpu_stage=False), 1000),
+    ("serial_sub_batches", dict(batch=300, serial=True), dict(), 1000),
+    ("fixed_entries", dict(fixed_entries=True), dict(fixed_entries="F"), 1000),
+    ("fixed_entries_no_gpu_stage", dict(fixed_entries=True, stage_mask=2), dict(fixed_entries="F",
+                                                                            use_gpu_stage=False), 1000),
 ]
+
+
+def _fixed_entries(tiny, E):
+    """The predefined entries of the library's fixed mode, from the oracle's buckets: entry
+    e is pivot e // r of bucket e % r."""
+    b = tiny["pivots"][tiny["buckets"]]
+    r = b.shape[0]
+    return np.array([b[e % r, e // r] for e in range(E)], dtype=np.int64)
 
 
 def test_search_forms_match_the_oracle(dev, tiny, lib_qr):
@@ -150,6 +162,7 @@ def test_search_forms_match_the_oracle(dev, tiny, lib_qr):
         say(f"Index.search form {name}: {nq} queries, k 10, ef 64/64")
         ids, d, cnt, st = idx.search(Q[:nq], 10, 64, 64, with_counters=True, **skw)
         outs.append((name, ids, d, cnt))
+        okw = {k: (_fixed_entries(tiny, 8) if v == "F" else v) for k, v in okw.items()}
         jobs.append((np.arange(nq), dict(k=10, ef_gpu=64, ef_cpu=64, E=8, **okw)))
     say("oracle pipeline for every form (host worker processes)")
     refs = oracle_jobs.pipeline(_arrays(tiny), jobs)
@@ -295,4 +308,35 @@ def test_ragged_traverse_matches_the_oracle(dev, tiny):
                 assert cnt[i, 1] == r["n_dist"]
     off = tally.done()
     say(f"  {m} queries, {bad} differ (near ties), {off} distances 1 ulp off")
+    assert bad <= max(1, m // 1000)
+
+
+def test_ragged_traverse_with_bloom_filter_and_width_two_matches_the_oracle(dev, tiny):
+    say("gpu_traverse with per-query ef in {8, 33, 64, 100}, the Bloom filter (2^15 bits) and width 2")
+    ent, _, _, _ = oracle_entries(tiny, 8)
+    rng = np.random.default_rng(6)
+    m = 300
+    efs = rng.choice([8, 33, 64, 100], size=m).astype(np.int32)
+    Qr = tiny["Qr32"][:m]
+    ids, d, cnt = pa.gpu_traverse_ragged(_t(Qr, dev), _t(tiny["Xr32"], dev), _t(tiny["sub_adj"].astype(np.int32), dev),
+                                         _t(ent[:m].astype(np.int32), dev), _t(efs, dev), bloom_log2=15, width=2)
+    ids, d, cnt = ids.cpu().numpy(), d.cpu().numpy(), cnt.cpu().numpy()
+    assert (cnt[:, 2] == 0).all()
+    ent_use = np.where(np.arange(8)[None, :] < np.minimum(efs, 8)[:, None], ent[:m], -1)
+    refs = oracle_jobs.traverse(Qr, tiny["Xr32"].astype(np.float64), tiny["sr"], tiny["sn"], ent_use,
+                                np.arange(m), efs, bloom_log2=15, width=2)
+    bad = 0
+    tally = DistTally()
+    for i, r in enumerate(refs):
+        ef = int(efs[i])
+        ref = np.full(ef, -1)
+        ref[:r["ids"].size] = r["ids"]
+        if not (ids[i, :ef] == ref).all():
+            assert r["margin"] <= TIE, (i, ef, r["margin"])
+            bad += 1
+            continue
+        tally.check(d[i, :r["ids"].size], r["dists"], i)
+        if r["margin"] > TIE:
+            assert cnt[i, 0] == r["n_exp"] and cnt[i, 1] == r["n_dist"]
+    tally.done()
     assert bad <= max(1, m // 1000)

@@ -482,3 +482,30 @@ def test_gpu_only_special_case_is_exact_knn_with_every_node_and_full_rank():
         assert (ids == gt).all()
         assert (d == gd.astype(np.float32).astype(np.float64)).all()
         assert (cnt[:, 0] == n).all() and (cnt[:, 2] == 0).all()
+
+
+def test_fixed_entries_pipeline_is_exact_at_large_ef_and_equals_fes_for_its_own_entries():
+    # without entry selection every query starts from the same predefined nodes; on a
+    # connected graph a list that holds every node still returns the exact kNN, with and
+    # without the GPU stage; and a query given its own FES entries as the fixed set gets
+    # the FES pipeline's result
+    X, rowptr, nbrs = _small_graph(seed=95)
+    n = X.shape[0]
+    Q = gmm_points(96, 5, 10, 3, stream_offset=1)
+    V, _, _ = oracle.fit_projection(X, 4)
+    Xr = oracle.project(X, V)
+    P_ids = np.arange(0, 64)
+    b, c = oracle.balanced_kmeans(Xr[P_ids], 2, [0, 1])
+    gt, _ = oracle.exact_knn(X, Q, 10)
+    for gpu in (True, False):
+        ids, _, _ = oracle.pipeline(Q, X, V, rowptr, nbrs, rowptr, nbrs, Xr, c, b, Xr[P_ids], P_ids, k=10,
+                                    ef_gpu=n, ef_cpu=n, E=1, use_gpu_stage=gpu, fixed_entries=[7])
+        assert (ids == gt).all()
+    Qr = oracle.as_f32(oracle.project(Q, V))
+    ent, _, _, _ = oracle.select_entries(Qr, c, b, Xr[P_ids], P_ids, 4)
+    for i in range(Q.shape[0]):
+        a = oracle.pipeline(Q[i:i + 1], X, V, rowptr, nbrs, rowptr, nbrs, Xr, c, b, Xr[P_ids], P_ids, k=5,
+                            ef_gpu=8, ef_cpu=8, E=4)
+        f = oracle.pipeline(Q[i:i + 1], X, V, rowptr, nbrs, rowptr, nbrs, Xr, c, b, Xr[P_ids], P_ids, k=5,
+                            ef_gpu=8, ef_cpu=8, E=4, fixed_entries=ent[i])
+        assert (a[0] == f[0]).all() and (a[1] == f[1]).all() and (a[2] == f[2]).all()
