@@ -73,24 +73,68 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def build_fixture(spec, device):
+def large(spec):
+    """Workloads whose exact kNN graph is out of reach (the IVF-restricted builder is used)."""
+    return spec.n >= 4_000_000
+
+
+def build_fixture(spec, device, cache=None, nprobe=8):
+    """Base set, queries, full graph and ground truth.  The graph of a large workload comes
+    from the IVF-restricted builder; ``cache`` (a directory) keeps the graph, the ground
+    truth and the subgraph between runs (the vectors are regenerated from their seeds)."""
     from synth import base_vectors, query_vectors, node_order, pivot_choice, kmeans_init_choice
     from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
+    from synth.ivf import build_graph_ivf, build_subgraph_csr_ivf
     from synth.knn import exact_knn
     t = time.time()
     X = base_vectors(spec)
     Q = query_vectors(spec)
     log(f"data {X.shape} + {Q.shape} in {time.time() - t:.1f}s")
-    t = time.time()
-    adj = build_graph(X, spec.degree, device=device)
+    tag = f"{spec.name}_n{spec.n}_q{spec.queries}_R{spec.degree}_p{nprobe}"
+    path = (lambda what: os.path.join(cache, f"{tag}_{what}.npy")) if cache else None
+    if cache and os.path.exists(path("adj")) and os.path.exists(path("gt")):
+        adj, gt = np.load(path("adj")), np.load(path("gt"))
+        log(f"graph and ground truth from {cache}")
+    else:
+        t = time.time()
+        if large(spec):
+            adj = build_graph_ivf(X, spec.degree, nprobe=nprobe, seed=spec.seed, device=device, log=log)
+        else:
+            adj = build_graph(X, spec.degree, device=device)
+        log(f"full graph: mean degree {(adj >= 0).sum(1).mean():.2f} in {time.time() - t:.1f}s")
+        t = time.time()
+        gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device)
+        log(f"ground truth in {time.time() - t:.1f}s")
+        if cache:
+            os.makedirs(cache, exist_ok=True)
+            np.save(path("adj"), adj)
+            np.save(path("gt"), gt)
     rp, nb = padded_to_csr(adj)
-    log(f"full graph: mean degree {(adj >= 0).sum(1).mean():.2f} in {time.time() - t:.1f}s")
-    t = time.time()
-    gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device)
-    log(f"ground truth in {time.time() - t:.1f}s")
+    if large(spec):
+        def sub_builder(Xa, mask, R, device=None):
+            return build_subgraph_csr_ivf(Xa, mask, R, nprobe=nprobe, seed=spec.seed + 3, device=device, log=log)
+    else:
+        sub_builder = build_subgraph_csr
+    if cache:
+        def cached_sub(Xa, mask, R, device=None, _b=sub_builder):
+            f = os.path.join(cache, f"{tag}_sub_{int(mask.sum())}.npz")
+            if os.path.exists(f):
+                with np.load(f) as d:
+                    if d["mask"].shape == mask.shape and (d["mask"] == mask).all():
+                        log(f"subgraph from {cache}")
+                        return d["sr"], d["sn"]
+            sr, sn = _b(Xa, mask, R, device=device)
+            np.savez(f + ".tmp.npz", mask=mask, sr=sr, sn=sn)
+            os.replace(f + ".tmp.npz", f)
+            return sr, sn
+        builder = cached_sub
+    else:
+        builder = sub_builder
     return dict(X=X, Q=Q, adj=adj, rp=rp, nb=nb, gt=gt, order=node_order(spec.n, spec.seed),
                 pivot_choice=pivot_choice, kmeans_init_choice=kmeans_init_choice,
-                build_subgraph_csr=build_subgraph_csr, device=device)
+                build_subgraph_csr=builder, device=device,
+                graph="IVF-restricted candidates (%d lists of ~1,024 rows probed)" % nprobe if large(spec)
+                else "exact candidates")
 
 
 def build_index(spec, fx, xr_dtype, shared, compact=False):
@@ -392,6 +436,62 @@ def roofline(spec, agg, steps, ef, E, xr_bytes, form, visited=None):
             "avg_launch_ms": round(avg_ms, 4), "launches": int(launches)}
 
 
+def precision_leg(idx, spec, fx, shared, form, ef, n=1000):
+    """Distance error of a form against fp64 on its unquantised reduced vectors, at stage 1
+    and at the output, on the first n queries.  Stage 1 runs through the stage-isolated
+    calls on the same tables the index holds (the projection kernel rounds X V to the
+    form, the pivots' fp32 rows feed entry selection), and returns correctly rounded
+    distances of the stored rows; the reference is the fp64 distance between Q V and X V
+    (V the fp32 projection).  The output distances are the host stages' full distances,
+    compared with fp64 full distances."""
+    import torch
+    import paper_2503_21206_amd as pa
+    dev = torch.device("cuda")
+    n = min(n, spec.queries)
+    V = shared["V"]
+    Vt = torch.as_tensor(V).to(dev)
+    mask, sr, sn = shared["sub"]
+    _, buckets, cent = idx.state()
+    Xd = torch.as_tensor(fx["X"]).to(dev)
+    Xr = pa.project(Xd, Vt, form)
+    del Xd
+    piv = buckets.reshape(-1).astype(np.int64)
+    EV = pa.project(torch.as_tensor(fx["X"][piv]).to(dev), Vt, "f32").reshape(spec.r, -1, spec.d_r)
+    EVn = (EV.double() ** 2).sum(-1).float()
+    EVid = torch.as_tensor(buckets).to(dev)
+    Q = fx["Q"][:n]
+    Qr, cl = pa.project_route(torch.as_tensor(Q).to(dev), Vt, torch.as_tensor(cent).to(dev))
+    E = min(ef[0], spec.n_pivots // spec.r)
+    ent, _ = pa.select_entries(Qr, cl, EV.contiguous(), EVn, EVid, E, spec.metric)
+    R_sub = int((sr[1:] - sr[:-1]).max())
+    adj = pa.pack_adjacency(sr, sn, R_sub)
+    ids, d, _ = pa.gpu_traverse(Qr, Xr, adj, ent, ef[0], spec.metric)
+    torch.cuda.synchronize()
+    ids, d = ids.cpu().numpy(), d.cpu().numpy().astype(np.float64)
+    del Xr, adj
+    ok = ids >= 0
+    V64 = V.astype(np.float64)
+    q64 = Q.astype(np.float64) @ V64
+    rows = fx["X"][ids[ok]].astype(np.float64) @ V64
+    qq = q64[np.nonzero(ok)[0]]
+    ref = ((qq - rows) ** 2).sum(1) if spec.metric == "l2" else -(qq * rows).sum(1)
+    err1 = np.abs(d[ok] - ref) / np.maximum(np.abs(ref), 1e-30)
+    oi, od, _, _ = idx.search(Q, spec.k, ef[0], ef[1])
+    okk = oi >= 0
+    xo = fx["X"][oi[okk]].astype(np.float64)
+    qo = Q.astype(np.float64)[np.nonzero(okk)[0]]
+    ref_o = ((qo - xo) ** 2).sum(1) if spec.metric == "l2" else -(qo * xo).sum(1)
+    err_o = np.abs(od[okk].astype(np.float64) - ref_o) / np.maximum(np.abs(ref_o), 1e-30)
+    out = {"queries": n, "stage1_max_rel_err": float(f"{err1.max():.3g}"),
+           "stage1_mean_rel_err": float(f"{err1.mean():.3g}"),
+           "output_max_rel_err": float(f"{err_o.max():.3g}"),
+           "what": "max/mean |delta - delta_64| / |delta_64| over every returned (id, distance): stage 1 against "
+                   "fp64 distances of the unquantised reduced vectors (Q V, X V), output against fp64 full "
+                   "distances"}
+    log(f"  precision {form}: {out}")
+    return out
+
+
 def memory_leg(spec, fx, shared, ef, full_info, steps):
     """Memory-bounded layout (X_r and the device subgraph for the sampled nodes only, fp16
     rows) at several sampling ratios: HBM held by the index (and the library's model of
@@ -691,6 +791,13 @@ def main():
                     help="skip the flat-mixture leg (the same shape, centres ~ N(0, 4I))")
     ap.add_argument("--ef", default="",
                     help="ef_gpu,ef_cpu to time directly instead of sweeping for the target recall")
+    ap.add_argument("--n", type=int, default=0,
+                    help="base rows (the first n rows of the workload's base set; 0: all of them)")
+    ap.add_argument("--queries", type=int, default=0, help="queries (the first ones; 0: the workload's count)")
+    ap.add_argument("--nprobe", type=int, default=8, help="IVF lists probed per row by the large-N graph builder")
+    ap.add_argument("--fixture-cache", default="",
+                    help="directory that keeps the graph, ground truth and subgraph between runs")
+    ap.add_argument("--no-precision", action="store_true", help="skip the per-form distance-error leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -703,8 +810,13 @@ def main():
     import paper_2503_21206_amd as pa
     from synth import SPECS
     pa.device_init(0)
+    import dataclasses
     spec = SPECS[args.workload]
-    fx = build_fixture(spec, "cuda")
+    if args.n:
+        spec = dataclasses.replace(spec, n=args.n)
+    if args.queries:
+        spec = dataclasses.replace(spec, queries=args.queries)
+    fx = build_fixture(spec, "cuda", cache=args.fixture_cache or None, nprobe=args.nprobe)
     shared = {}
     forms = {}
     serving = None
@@ -742,6 +854,17 @@ def main():
             "curve": curve,
         }
         log(f"{form}: ef={ef} recall={rec:.4f} qps={qps:,.0f} roofline={forms[form]['roofline']}")
+        if not args.no_precision:
+            forms[form]["precision"] = precision_leg(idx, spec, fx, shared, form, ef)
+            if form != "f32" and "f32" in forms and (forms["f32"]["ef_gpu"], forms["f32"]["ef_cpu"]) != ef:
+                e32 = (forms["f32"]["ef_gpu"], forms["f32"]["ef_cpu"])
+                _, _, rec32 = timed(idx, spec, fx, e32, 1, 0)
+                forms[form]["precision"]["recall_at_f32_ef"] = {"ef_gpu": e32[0], "ef_cpu": e32[1],
+                                                                "recall": round(rec32, 5)}
+            if form != "f32" and "f32" in forms:
+                r32 = forms["f32"]["recall"]
+                mine = forms[form]["precision"].get("recall_at_f32_ef", {}).get("recall", rec)
+                forms[form]["precision"]["recall_loss_vs_f32"] = round(r32 - mine, 5)
         if not args.no_bloom:  # stage-1 variants at the same ef
             variants = {"bloom": ("the Bloom-filter visited set of section 4.3 (automatic size, 32 bits per "
                                   "cache slot) instead of the exact cache", True, 1),
@@ -782,7 +905,7 @@ def main():
             rates = [float(x) for x in args.serve_rates.split(",") if x]
             serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
         idx.close()
-    if args.flat and not args.no_extra:
+    if args.flat and not args.no_extra and args.workload + "_flat" in SPECS and not args.n:
         log("flat mixture (centres ~ N(0, 4I)) at the same shape")
         extra["flat_mixture"] = flat_leg(args, SPECS[args.workload + "_flat"])
     main_form = "f32" if "f32" in forms else next(iter(forms))
@@ -793,9 +916,10 @@ def main():
         "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{spec.name}: N={spec.n} d={spec.dim} {spec.metric} k={spec.k} "
-                               f"{spec.components}-component GMM, {spec.queries} queries, degree {spec.degree}, "
+                               f"{spec.components}-component {'mixture' if spec.kind != 'aniso' else 'anisotropic mixture'}"
+                               f", {spec.queries} queries, degree {spec.degree}, "
                                f"d_r={spec.d_r}, rho={spec.rho} {spec.sample_mode}, {spec.n_pivots} pivots/"
-                               f"{spec.r} buckets", "ef_gpu": f["ef_gpu"], "ef_cpu": f["ef_cpu"],
+                               f"{spec.r} buckets; graph from {fx['graph']}", "ef_gpu": f["ef_gpu"], "ef_cpu": f["ef_cpu"],
                    "recall": f["recall"],
                    "host_threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))},
         "roofline": f["roofline"],

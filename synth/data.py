@@ -164,12 +164,24 @@ def _rows(spec: WorkloadSpec, stream_seed: int, total: int, start: int, stop: in
     start, stop = max(0, start), min(total, stop)
     out = np.empty((max(0, stop - start), spec.dim), dtype=np.float32)
     c0, c1 = start // CHUNK, (stop - 1) // CHUNK if stop > start else -1
-    for c in range(c0, c1 + 1):
+
+    def fill(c):
         lo, hi = c * CHUNK, min(total, (c + 1) * CHUNK)
         block = _chunk_rows(spec.seed, stream_seed, c, hi - lo, spec.components, spec.dim,
                             spec.kind, model)
         a, b = max(lo, start), min(hi, stop)
         out[a - start:b - start] = block[a - lo:b - lo]
+
+    # chunks draw from their own streams, so their order of generation does not matter;
+    # NumPy releases the interpreter lock while it fills them
+    chunks = range(c0, c1 + 1)
+    if len(chunks) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(16, len(chunks))) as ex:
+            list(ex.map(fill, chunks))
+    else:
+        for c in chunks:
+            fill(c)
     return out
 
 

@@ -37,9 +37,14 @@ def _pair_dist64(vecs: torch.Tensor) -> torch.Tensor:
 
 @torch.no_grad()
 def rng_prune(x64: torch.Tensor, cand: torch.Tensor, cdist: torch.Tensor, R: int,
-              keep_all_if_fits: bool = False, chunk: int = 8192) -> torch.Tensor:
-    """HNSW-style selection over sorted candidate rows; returns kept ids [n][R] (-1 pad)."""
+              keep_all_if_fits: bool = False, chunk: int = 0) -> torch.Tensor:
+    """HNSW-style selection over sorted candidate rows; returns kept ids [n][R] (-1 pad).
+    Rows are processed in chunks (0: sized so that a chunk's gathered vectors take about
+    1 GiB on a GPU, 8,192 rows on the CPU); every row is decided on its own."""
     n, c = cand.shape
+    if chunk <= 0:
+        chunk = 8192 if cand.device.type != "cuda" else \
+            max(8192, min(1 << 16, (1 << 30) // max(1, c * x64.shape[1] * 8)))
     out = torch.full((n, R), -1, dtype=torch.int64, device=cand.device)
     for a in range(0, n, chunk):
         ci = cand[a:a + chunk]
@@ -70,36 +75,52 @@ def rng_prune(x64: torch.Tensor, cand: torch.Tensor, cdist: torch.Tensor, R: int
 
 
 @torch.no_grad()
-def _add_reverse(x64: torch.Tensor, fwd: torch.Tensor, R: int) -> torch.Tensor:
-    """Union of forward rows and nearest-R reverse candidates, re-pruned to R."""
+def add_reverse(x64: torch.Tensor, fwd: torch.Tensor, R: int, block: int = 1 << 22) -> torch.Tensor:
+    """Every row's forward neighbours united with the rows that point to it, cut to the
+    nearest 2R by (fp64 distance, id) and re-pruned to R (rows holding at most R keep all).
+    The proposals are gathered one block of target rows at a time, so that memory stays
+    bounded at 10^8 rows."""
     dev = fwd.device
     n = fwd.shape[0]
-    src = torch.arange(n, device=dev)[:, None].expand_as(fwd)
-    m = fwd >= 0
-    s, d = src[m], fwd[m]
-    # forward (s -> d) and reverse (d -> s) proposals
-    node = torch.cat([s, d])
-    nbr = torch.cat([d, s])
-    key = torch.unique(node * n + nbr)
-    node, nbr = key // n, key % n
-    dist = ((x64[node] - x64[nbr]) ** 2).sum(-1)
-    # group by node, ascending (dist, id)
-    o = torch.argsort(nbr, stable=True)
-    node, nbr, dist = node[o], nbr[o], dist[o]
-    o = torch.argsort(dist, stable=True)
-    node, nbr, dist = node[o], nbr[o], dist[o]
-    o = torch.argsort(node, stable=True)
-    node, nbr, dist = node[o], nbr[o], dist[o]
-    counts = torch.bincount(node, minlength=n)
-    starts = torch.cumsum(counts, 0) - counts
-    rank = torch.arange(node.shape[0], device=dev) - starts[node]
     width = 2 * R
-    sel = rank < width
-    cand = torch.full((n, width), -1, dtype=torch.int64, device=dev)
-    cd = torch.full((n, width), float("inf"), dtype=torch.float64, device=dev)
-    cand[node[sel], rank[sel]] = nbr[sel]
-    cd[node[sel], rank[sel]] = dist[sel]
-    return rng_prune(x64, cand, cd, R, keep_all_if_fits=True)
+    pairs = max(1 << 16, (1 << 31) // (8 * x64.shape[1]))  # ~2 GiB per gathered operand
+    out = torch.full((n, R), -1, dtype=torch.int64, device=dev)
+    for a in range(0, n, block):
+        b = min(n, a + block)
+        nb_ = b - a
+        f = fwd[a:b]
+        fm = f >= 0
+        node_f = torch.arange(a, b, device=dev)[:, None].expand_as(f)[fm]
+        nbr_f = f[fm]
+        # reverse proposals: the sources u of edges u -> v with v in [a, b)
+        hit = (fwd >= a) & (fwd < b)
+        src, col = torch.nonzero(hit, as_tuple=True)
+        node_r = fwd[src, col]
+        del hit, col
+        key = torch.unique(torch.cat([node_f - a, node_r - a]) * n + torch.cat([nbr_f, src]))
+        del node_f, nbr_f, node_r, src
+        node, nbr = key // n + a, key % n
+        del key
+        dist = torch.empty(node.shape[0], dtype=torch.float64, device=dev)
+        for p in range(0, node.shape[0], pairs):
+            dist[p:p + pairs] = ((x64[node[p:p + pairs]] - x64[nbr[p:p + pairs]]) ** 2).sum(-1)
+        # group by node, ascending (dist, id)
+        o = torch.argsort(nbr, stable=True)
+        node, nbr, dist = node[o], nbr[o], dist[o]
+        o = torch.argsort(dist, stable=True)
+        node, nbr, dist = node[o], nbr[o], dist[o]
+        o = torch.argsort(node, stable=True)
+        node, nbr, dist = node[o], nbr[o], dist[o]
+        counts = torch.bincount(node - a, minlength=nb_)
+        starts = torch.cumsum(counts, 0) - counts
+        rank = torch.arange(node.shape[0], device=dev) - starts[node - a]
+        sel = rank < width
+        cand = torch.full((nb_, width), -1, dtype=torch.int64, device=dev)
+        cd = torch.full((nb_, width), float("inf"), dtype=torch.float64, device=dev)
+        cand[node[sel] - a, rank[sel]] = nbr[sel]
+        cd[node[sel] - a, rank[sel]] = dist[sel]
+        out[a:b] = rng_prune(x64, cand, cd, R, keep_all_if_fits=True)
+    return out
 
 
 def _csr(adj: np.ndarray, n: int) -> csr_matrix:
@@ -128,11 +149,16 @@ def _append(adj: np.ndarray, u: int, v: int) -> bool:
 
 
 def _repair(X: np.ndarray, adj: np.ndarray, medoid: int, device) -> np.ndarray:
+    return _repair_with(X, adj, medoid, device, _reached_from)
+
+
+def _repair_with(X: np.ndarray, adj: np.ndarray, medoid: int, device, reached_fn) -> np.ndarray:
     """Link one node of every source strongly connected component of the unreached part
-    from its nearest reached node (with a free slot); repeat until all are reached."""
+    from its nearest reached node (with a free slot); repeat until all are reached.
+    ``reached_fn(adj, start)`` gives the rows reachable from ``start`` (bool [n])."""
     n, R = adj.shape
     for _ in range(16):
-        reached = _reached_from(adj, medoid)
+        reached = reached_fn(adj, medoid)
         if reached.all():
             return adj
         un = np.nonzero(~reached)[0]
@@ -157,7 +183,7 @@ def _repair(X: np.ndarray, adj: np.ndarray, medoid: int, device) -> np.ndarray:
             if not _append(adj, int(h), int(u)):
                 adj[int(h), -1] = u
             _append(adj, int(u), int(h))
-    if not _reached_from(adj, medoid).all():
+    if not reached_fn(adj, medoid).all():
         raise RuntimeError("connectivity repair did not converge")
     return adj
 
@@ -181,7 +207,7 @@ def build_graph(X: np.ndarray, R: int, cand: int | None = None, *, device=None,
     ci = torch.as_tensor(ids).to(dev)
     cd = torch.as_tensor(dist).to(dev)
     fwd = rng_prune(x64, ci, cd, R)
-    full = _add_reverse(x64, fwd, R)
+    full = add_reverse(x64, fwd, R)
     adj = full.cpu().numpy()
     # rows sorted by (distance, id)
     adj = _sort_rows(X, adj, dev)
