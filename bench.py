@@ -103,7 +103,8 @@ def build_fixture(spec, device, cache=None, nprobe=8):
             adj = build_graph(X, spec.degree, device=device)
         log(f"full graph: mean degree {(adj >= 0).sum(1).mean():.2f} in {time.time() - t:.1f}s")
         t = time.time()
-        gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device)
+        gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device,
+                          budget_bytes=(32 << 30) if large(spec) else None)
         log(f"ground truth in {time.time() - t:.1f}s")
         if cache:
             os.makedirs(cache, exist_ok=True)
@@ -798,6 +799,9 @@ def main():
     ap.add_argument("--fixture-cache", default="",
                     help="directory that keeps the graph, ground truth and subgraph between runs")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-form distance-error leg")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="time only the MFMA kernels (projection, FES) on synthetic inputs of the workload's "
+                         "shape and print their JSON; no fixture, no search")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -816,6 +820,14 @@ def main():
         spec = dataclasses.replace(spec, n=args.n)
     if args.queries:
         spec = dataclasses.replace(spec, queries=args.queries)
+    if args.kernels_only:
+        from synth import query_vectors
+        from synth.data import make_rng
+        Qk = query_vectors(spec)
+        Vk = np.linalg.qr(make_rng(spec.seed, 91).standard_normal((spec.dim, spec.d_r)))[0].astype(np.float32)
+        print(json.dumps({"kernels": gemm_leg(spec, {"Q": Qk}, Vk),
+                          "workload": f"{spec.name} query shape, random orthonormal projection"}), flush=True)
+        return
     fx = build_fixture(spec, "cuda", cache=args.fixture_cache or None, nprobe=args.nprobe)
     shared = {}
     forms = {}

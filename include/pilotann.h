@@ -165,14 +165,17 @@ pa_status pa_build_entries(const float* P_host, int32_t n_p, int32_t d, int32_t 
                            float* centroids_host);
 
 /* FES scoring and top-E (Algorithm 2 with a fused top-E): every query i is scored only
- * against the n_b pivots of its cluster cluster_dev[i] (from pa_project_route), on MFMA:
- * delta = ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP), fp32.  EV_dev [r][n_b][d] fp32
- * bucket-major pivot vectors, EVnorm_dev [r][n_b] fp32 squared norms, EVid_dev [r][n_b]
- * int32 node ids.  Outputs ids_dev [m][E] int32 and d_dev [m][E] fp32 ordered by
- * (delta, id), padded with (-1, +inf) when E > n_b.  d % 16 == 0.  Buckets of up to 512
- * pivots are scored in one pass per 16-query tile; larger buckets are scanned in chunks
- * with a running top-E per query (same results).
- * Results of a query do not depend on the other queries of the batch. */
+ * against the n_b pivots of its cluster cluster_dev[i] (from pa_project_route), on MFMA in
+ * the expanded form ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP), fp32, together with a
+ * rigorous bound on each score's rounding error.  Only pivots whose error interval can
+ * still reach the E-th smallest upper bound are kept, and those are re-scored exactly, so
+ * the result is the exact top E: ids_dev [m][E] int32 and d_dev [m][E] fp32, the
+ * correctly rounded distance (squared L2 or -IP, direct form), ordered by (distance,
+ * id), padded with (-1, +inf) when E > n_b.  EV_dev [r][n_b][d] fp32 bucket-major pivot
+ * vectors, EVnorm_dev [r][n_b] fp32 squared norms, EVid_dev [r][n_b] int32 node ids.
+ * d % 16 == 0.  Buckets are scanned in chunks of 128 pivots per 16-query tile.
+ * PA_EUNSUPPORTED if a 16-query tile's candidate list (E + 192 entries) does not fit the
+ * device's LDS.  Results of a query do not depend on the other queries of the batch. */
 pa_status pa_select_entries(const float* Qr_dev, const int32_t* cluster_dev, int64_t m,
                             int32_t d, const float* EV_dev, const float* EVnorm_dev,
                             const int32_t* EVid_dev, int32_t r, int32_t n_b, int32_t E,
@@ -206,9 +209,10 @@ pa_status pa_quantize_fp8_rows(const float* X_host, int64_t n, int32_t d, uint8_
  * (v_mfma_f32_16x16x32_fp8_fp8, fp32 accumulation) on the pivots' e4m3 codes EV8_dev
  * [r][n_b][d] uint8 with row scales EVscale_dev [r][n_b] fp32 (pa_quantize_fp8_rows) and the
  * queries encoded the same way on the fly; the K best pivots of that approximate score
- * (E <= K) are re-scored in fp32 from EV_dev (direct form: ||q - p||^2 or -q.p) and the best
- * E by (fp32 distance, id) are returned.  d % 32 == 0.  PA_EUNSUPPORTED if the K-list of a
- * 16-query tile does not fit the device's LDS. */
+ * (ties by position in the bucket; E <= K) are re-scored exactly from EV_dev (direct form:
+ * ||q - p||^2 or -q.p, correctly rounded fp32) and the best E by (distance, id) are
+ * returned.  d % 32 == 0.  PA_EUNSUPPORTED if the K-list of a 16-query tile (K + 128
+ * entries) does not fit the device's LDS. */
 pa_status pa_select_entries_fp8(const float* Qr_dev, const int32_t* cluster_dev, int64_t m, int32_t d,
                                 const float* EV_dev, const uint8_t* EV8_dev, const float* EVscale_dev,
                                 const float* EVnorm_dev, const int32_t* EVid_dev, int32_t r, int32_t n_b,

@@ -5,12 +5,13 @@
 // counting sort into a preallocated permutation - no allocation, as section 5 asks), and
 // then every block works on one (cluster, 16-query tile) pair: a 16 x n_b x d product on
 // MFMA against that cluster's bucket of pivots, the distance epilogue fused, a running
-// pre-selection per query in LDS, and an exact re-score of the pre-selected pivots before
-// the top-E is emitted.  The m x n distance matrix D of Algorithm 2 is never stored.
+// candidate list per query in LDS, and an exact re-score of the candidates before the
+// top-E is emitted.  The m x n distance matrix D of Algorithm 2 is never stored.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "ffloat.hpp"
@@ -22,9 +23,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTQ = 16;          // queries per tile (MFMA rows)
 constexpr int kMaxClusters = 64;
-constexpr int kRerankSlack = 16; // FP32 form pre-selects E + 16 pivots for the exact re-score
-constexpr int kWaves = 16;       // one wavefront per query row of a tile: the per-row sorts and
-                                 // re-scores are latency bound, so every row gets its own wave
+constexpr int kWaves = 16;       // one wavefront per query row of a tile: the per-row selection
+                                 // and re-scores are latency bound, so every row gets its own wave
 constexpr int kThreads = 64 * kWaves;
 
 __device__ __forceinline__ uint32_t ord_f32(float f) {
@@ -80,19 +80,31 @@ __global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------- pivot scoring
-// Any bucket size.  Each query row keeps a running list of its best K2 = next_pow2(K)
-// keys (ascending) in LDS.  The bucket is scanned in chunks of K2 pivots, scored on MFMA
-// into an approximate distance in the expanded form |q|^2 + |p|^2 - 2 q.p (FP32 form:
-// v_mfma_f32_16x16x4f32; FP8 form: queries encoded per row like the pivots, scale =
-// max|q| / 448, e4m3 round to nearest even, then v_mfma_f32_16x16x32_fp8_fp8); the
-// row's wavefront sorts the chunk descending, keeps the elementwise smaller of list and
-// chunk (the lower half of a bitonic merge) and merges it back into ascending order.
-// Pre-selection keys carry the pivot's index in its bucket.  The K pre-selected pivots
-// are then re-scored in the direct form with float-float arithmetic, so the emitted
-// distances are the correctly rounded fp32 ones, and the top E by (distance, node id) is
-// emitted.  FP32 form: K = E + 16, so an exact top-E member is lost only if more than 16
-// pivots fall within the expanded form's rounding error of it; FP8 form: K is a multiple
-// of E that absorbs the e4m3 error.
+// One block per (cluster, 16-query tile); one wavefront per query row of the tile.
+//
+// The bucket is scanned in chunks of kCH pivots.  Per chunk the block scores the 16 x kCH
+// tile on MFMA in the expanded form ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP): FP32
+// form v_mfma_f32_16x16x4f32; FP8 form v_mfma_f32_16x16x32_fp8_fp8 on per-row e4m3 codes
+// (queries encoded on the fly like the pivots: scale = max|q| / 448, round to nearest
+// even).  Each row's wavefront then offers the chunk's pivots to the row's candidate
+// buffer in LDS and shrinks the buffer when it fills:
+//
+// * FP32 form (exact).  Each score comes with a rigorous bound eps on its error (the
+//   expanded form in fp32: products, their sum, the norms and the final fma each add at
+//   most a few units of 2^-24 of (||q||^2 + ||p||^2 + |score|) per term, and eps takes
+//   4 (d + 4) of them).  T is the E-th smallest upper end score + eps among the pivots
+//   seen so far; a pivot whose lower end score - eps exceeds T has at least E pivots
+//   certainly closer and can never be in the top E.  Every other pivot stays.  At the end
+//   the survivors (typically E and a few near the boundary) are re-scored exactly: direct
+//   form in float-float, the correctly rounded fp32 distance, independent of summation
+//   order; the top E by (distance, node id) are emitted in order.  The result is the exact
+//   top E, whatever the rounding of the MFMA pass.
+// * FP8 form (approximate, the paper's reduced-precision selection).  The buffer keeps the
+//   K best pivots by (FP8 score, position); these are re-scored exactly and the top E by
+//   (distance, node id) are emitted.
+//
+// The E-th / K-th smallest value of a buffer is found by a bitwise search over the ordered
+// encoding (one ballot per buffer slot and bit), so no sort runs before the final E.
 typedef long fp8x8 __attribute__((ext_vector_type(1)));
 
 __device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
@@ -116,6 +128,8 @@ __device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
     return sign | static_cast<uint8_t>((exp8 << 3) | ((m >> 20) & 7u));
 }
 
+constexpr int kCH = 128;  // pivots per chunk: 8 MFMA column blocks
+
 struct FesArgs {
     const float* Qr;
     int d;
@@ -124,106 +138,274 @@ struct FesArgs {
     const float* EVscale;
     const float* EVnorm;
     const int32_t* EVid;
-    int r, n_b, E, K, K2, CH, P, metric;  // K2 = next power of two >= K
+    int r, n_b, E, K, cap, metric;  // K: FP8 pre-selection size; cap: buffer entries per row
     const int32_t* scratch;
     int32_t* out_ids;
     float* out_d;
 };
-
-// Bitonic sort of s[0, n) (n a power of two) by one wavefront, ascending or descending.
-__device__ void bitonic_sort(uint64_t* s, int n, int lane, bool descending) {
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < n; i += 64) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t x = s[i], y = s[l];
-                    const bool up = ((i & k) == 0) != descending;
-                    if ((x > y) == up) {
-                        s[i] = y;
-                        s[l] = x;
-                    }
-                }
-            }
-            wave_sync();
-        }
-    }
-}
-
-// Ascending order of a bitonic sequence s[0, n) (n a power of two).
-__device__ void bitonic_merge(uint64_t* s, int n, int lane) {
-    for (int j = n >> 1; j > 0; j >>= 1) {
-        for (int i = lane; i < n; i += 64) {
-            const int l = i ^ j;
-            if (l > i) {
-                const uint64_t x = s[i], y = s[l];
-                if (x > y) {
-                    s[i] = y;
-                    s[l] = x;
-                }
-            }
-        }
-        wave_sync();
-    }
-}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __builtin_bit_cast(float,
                               __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
+__device__ __forceinline__ int mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
 
-template <bool FP8>
+// Smallest v with #{valid x_i <= v} >= k (k >= 1, at least k valid entries), over S values
+// per lane; bitwise from the top, one ballot per slot and bit.
+template <typename T, int BITS, int S>
+__device__ T kth_smallest(const T (&x)[S], const bool (&ok)[S], int slots, int k) {
+    T v = 0;
+    for (int bit = BITS - 1; bit >= 0; --bit) {
+        const T probe = v | ((T(1) << bit) - 1);
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < slots) c += __popcll(__ballot(ok[i] && x[i] <= probe));
+        if (c < k) v |= T(1) << bit;
+    }
+    return v;
+}
+
+// The state of one row: its candidate buffer in LDS and the running threshold.  An entry
+// is (ordered value << 32) | position in the bucket, plus (FP32 form) the bound of the
+// value's error, 0 once the value is exact.  S slots per lane hold up to 64 S entries.
+template <bool FP8, int S>
+struct Row {
+    const FesArgs& a;
+    int64_t cb;
+    int lane, cnt = 0;
+    uint64_t* key;  // [cap]
+    float* eps;     // [cap] (FP32 form)
+    uint32_t T32 = 0xFFFFFFFFu;  // FP32 form: ordered upper-bound threshold
+    uint64_t T64 = ~0ull;        // FP8 form: ordered (score, position) threshold
+
+    __device__ Row(const FesArgs& args, int64_t cb_, uint64_t* k, float* e, int l)
+        : a(args), cb(cb_), lane(l), key(k), eps(e) {}
+
+    __device__ static bool finite(float v) { return fabsf(v) <= 3.0e38f; }
+    __device__ static uint32_t lo_ord(float v, float e) { return ord_f32(v - e); }
+    __device__ static uint32_t hi_ord(float v, float e) { return ord_f32(v + e); }
+
+    // Offer one pivot per lane (ok: the lane holds one).
+    __device__ void offer(bool ok, float v, float e, int pos) {
+        const uint64_t k = (static_cast<uint64_t>(ord_f32(v)) << 32) | static_cast<uint32_t>(pos);
+        bool admit;
+        if (FP8) admit = ok && k <= T64;
+        else admit = ok && (!finite(v) || lo_ord(v, e) <= T32);
+        const uint64_t m = __ballot(admit);
+        if (admit) {
+            const int at = cnt + mbcnt(m);
+            key[at] = k;
+            if (!FP8) eps[at] = e;
+        }
+        cnt += __popcll(m);
+        wave_sync();
+    }
+
+    __device__ void load(uint64_t (&kk)[S], float (&ee)[S], bool (&ok)[S], int slots) const {
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int t = i * 64 + lane;
+            ok[i] = i < slots && t < cnt;
+            kk[i] = ok[i] ? key[t] : ~0ull;
+            ee[i] = (!FP8 && ok[i]) ? eps[t] : 0.0f;
+        }
+    }
+
+    __device__ void store_kept(const uint64_t (&kk)[S], const float (&ee)[S], const bool (&keep)[S], int slots) {
+        wave_sync();
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i < slots) {
+                const uint64_t m = __ballot(keep[i]);
+                if (keep[i]) {
+                    const int at = n + mbcnt(m);
+                    key[at] = kk[i];
+                    if (!FP8) eps[at] = ee[i];
+                }
+                n += __popcll(m);
+            }
+        }
+        cnt = n;
+        wave_sync();
+    }
+
+    // Drops the entries that can no longer be among the best `want`.
+    __device__ void shrink(int want) {
+        if (cnt <= want) return;
+        const int slots = (cnt + 63) / 64;
+        uint64_t kk[S];
+        float ee[S];
+        bool ok[S], keep[S];
+        load(kk, ee, ok, slots);
+        if (FP8) {
+            T64 = kth_smallest<uint64_t, 64, S>(kk, ok, slots, want);
+#pragma unroll
+            for (int i = 0; i < S; ++i) keep[i] = ok[i] && kk[i] <= T64;
+        } else {
+            uint32_t ub[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const float v = unord_f32(static_cast<uint32_t>(kk[i] >> 32));
+                // a value outside the finite range never bounds T and is never dropped
+                ub[i] = (ok[i] && finite(v)) ? hi_ord(v, ee[i]) : 0xFFFFFFFFu;
+            }
+            const uint32_t t = kth_smallest<uint32_t, 32, S>(ub, ok, slots, want);
+            T32 = t < T32 ? t : T32;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const float v = unord_f32(static_cast<uint32_t>(kk[i] >> 32));
+                keep[i] = ok[i] && (!finite(v) || lo_ord(v, ee[i]) <= T32);
+            }
+        }
+        store_kept(kk, ee, keep, slots);
+    }
+
+    // Re-scores every entry exactly: four lanes per pivot, each over a quarter of the
+    // dimensions in float-float (pieces of up to 32 elements, all loads of a piece issued
+    // before its arithmetic), combined symmetrically across the quad, so the value is the
+    // correctly rounded distance whatever the summation order.  Sixteen pivots per pass.
+    __device__ void rescore(const float* qv) {
+        const int d = a.d, per = d / 4, sub = lane & 3;
+        for (int base = 0; base < cnt; base += 16) {
+            const int t = base + (lane >> 2);
+            const bool live = t < cnt;
+            const int pos = live ? static_cast<int>(key[t] & 0xFFFFFFFFu) : 0;
+            const float4* pv = reinterpret_cast<const float4*>(a.EV + (cb + pos) * d + sub * per);
+            const float* q4 = qv + sub * per;
+            ff32 acc{0.0f, 0.0f};
+            for (int seg = 0; seg < per; seg += 32) {
+                const int n4 = min(32, per - seg) / 4;
+                float4 x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = (u < n4 && live) ? pv[seg / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    if (u < n4) {
+                        const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            if (a.metric == PA_METRIC_L2) ff_add_sqdiff(acc, q4[seg + 4 * u + c], xv[c]);
+                            else ff_add_prod(acc, q4[seg + 4 * u + c], xv[c]);
+                        }
+                    }
+                }
+            }
+            acc = ff_add(acc, ff32{dpp<0xB1>(acc.hi), dpp<0xB1>(acc.lo)});  // lane ^ 1
+            acc = ff_add(acc, ff32{dpp<0x4E>(acc.hi), dpp<0x4E>(acc.lo)});  // lane ^ 2
+            const float v = (a.metric == PA_METRIC_L2) ? acc.hi : -acc.hi;
+            if (live && sub == 0) {
+                key[t] = (static_cast<uint64_t>(ord_f32(v)) << 32) | static_cast<uint32_t>(pos);
+                if (!FP8) eps[t] = 0.0f;
+            }
+        }
+        wave_sync();
+    }
+
+    // Exact values: keeps the best `want` by (distance, node id) (distinct: the node ids of
+    // a bucket are distinct).  Returns the largest kept distance's ordered encoding.
+    __device__ uint32_t keep_best(int want) {
+        const int slots = (cnt + 63) / 64;
+        uint64_t kk[S], nk[S];
+        float ee[S];
+        bool ok[S], keep[S];
+        load(kk, ee, ok, slots);
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            nk[i] = ok[i] ? ((kk[i] & 0xFFFFFFFF00000000ull) |
+                             static_cast<uint32_t>(a.EVid[cb + static_cast<int64_t>(kk[i] & 0xFFFFFFFFu)]))
+                          : ~0ull;
+        const uint64_t t = cnt > want ? kth_smallest<uint64_t, 64, S>(nk, ok, slots, want) : ~0ull;
+#pragma unroll
+        for (int i = 0; i < S; ++i) keep[i] = ok[i] && nk[i] <= t;
+        store_kept(kk, ee, keep, slots);
+        return static_cast<uint32_t>(t >> 32);
+    }
+
+    // Rewrites the (exact) entries as (ordered distance << 32) | node id.
+    __device__ void to_node_ids() {
+        for (int t = lane; t < cnt; t += 64)
+            key[t] = (key[t] & 0xFFFFFFFF00000000ull) |
+                     static_cast<uint32_t>(a.EVid[cb + static_cast<int64_t>(key[t] & 0xFFFFFFFFu)]);
+        wave_sync();
+    }
+};
+
+template <bool FP8, int S>
 __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int d = a.d;
-    float* Aq = reinterpret_cast<float*>(smem);          // [kTQ][d]
-    float* qn = Aq + kTQ * d;                           // [kTQ]
-    float* qs = qn + kTQ;                               // [kTQ]
-    uint8_t* Aq8 = reinterpret_cast<uint8_t*>(qs + kTQ); // [kTQ][d]
-    uint64_t* work = reinterpret_cast<uint64_t*>(Aq8 + ((kTQ * d + 15) / 16) * 16);  // [kTQ][P]
+    float* Aq = reinterpret_cast<float*>(smem);                      // [kTQ][d]
+    float* sc = Aq + kTQ * d;                                        // [kTQ][kCH] chunk scores
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(sc + kTQ * kCH);    // [kTQ][cap]
+    float* beps = reinterpret_cast<float*>(bkey + kTQ * a.cap);      // [kTQ][cap] (FP32 form)
+    uint8_t* Aq8 = reinterpret_cast<uint8_t*>(beps + (FP8 ? 0 : kTQ * a.cap));  // [kTQ][d] (FP8)
     __shared__ int qidx[kTQ];
+    __shared__ float qn[kTQ], qs[kTQ];
     __shared__ int s_c, s_cnt;
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int r = a.r, n_b = a.n_b, K = a.K, K2 = a.K2, CH = a.CH, P = a.P;
+    const int r = a.r, n_b = a.n_b;
     const int32_t* counts = a.scratch;
     const int32_t* offsets = a.scratch + r;
     const int32_t* tprefix = a.scratch + 2 * r + 1;
     const int32_t* perm = a.scratch + 3 * r + 2;
     const int b = blockIdx.x;
-    if (t == 0) {
-        int c = -1, cntq = 0;
-        if (b < tprefix[r]) {
-            c = 0;
-            while (c + 1 < r && tprefix[c + 1] <= b) ++c;
+    if (w == 0) {
+        // this block's cluster: the number of clusters whose tiles all come before tile b
+        // (the tile prefix is non-decreasing)
+        const bool before = lane < r && tprefix[lane + 1] <= b;
+        const int c = __popcll(__ballot(before));
+        int cntq = 0, base = 0;
+        if (c < r) {
             const int tile = b - tprefix[c];
-            const int base = offsets[c] + tile * kTQ;
+            base = offsets[c] + tile * kTQ;
             cntq = min(kTQ, counts[c] - tile * kTQ);
-            for (int i = 0; i < kTQ; ++i) qidx[i] = (i < cntq) ? perm[base + i] : -1;
         }
-        s_c = c;
-        s_cnt = cntq;
+        if (lane < kTQ) qidx[lane] = (c < r && lane < cntq) ? perm[base + lane] : -1;
+        if (lane == 0) {
+            s_c = c < r ? c : -1;
+            s_cnt = cntq;
+        }
     }
     __syncthreads();
     const int c = s_c;
     if (c < 0) return;
     const int cntq = s_cnt;
-    for (int idx = t; idx < kTQ * d; idx += kThreads) {
-        const int i = idx / d, j = idx - (idx / d) * d;
-        Aq[idx] = (i < cntq) ? a.Qr[static_cast<int64_t>(qidx[i]) * d + j] : 0.0f;
+    const int d4 = d / 4;
+    for (int idx = t; idx < kTQ * d4; idx += kThreads) {
+        const int i = idx / d4, j = idx - i * d4;
+        reinterpret_cast<float4*>(Aq)[idx] =
+            (i < cntq) ? reinterpret_cast<const float4*>(a.Qr + static_cast<int64_t>(qidx[i]) * d)[j]
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    for (int idx = t; idx < kTQ * P; idx += kThreads) work[idx] = ~0ull;
     __syncthreads();
-    if (t < kTQ) {
+    {  // the row's squared norm and FP8 scale (one wavefront per row)
         float s2 = 0.0f, amax = 0.0f;
-        for (int j = 0; j < d; ++j) {
-            const float x = Aq[t * d + j];
+        for (int j = lane; j < d; j += 64) {
+            const float x = Aq[w * d + j];
             s2 = __builtin_fmaf(x, x, s2);
             amax = fmaxf(amax, fabsf(x));
         }
-        qn[t] = s2;
-        qs[t] = amax > 0.0f ? amax / 448.0f : 1.0f;
+        s2 = wave_sum(s2);
+        amax = wave_max(amax);
+        if (lane == 0) {
+            qn[w] = s2;
+            qs[w] = amax > 0.0f ? amax / 448.0f : 1.0f;
+        }
     }
     __syncthreads();
     if (FP8) {
@@ -232,128 +414,99 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     }
 
     const int64_t cb = static_cast<int64_t>(c) * n_b;
-    const int nblk = CH / 16;
-    for (int c0 = 0; c0 < n_b; c0 += CH) {
-        for (int pb = w; pb < nblk; pb += kWaves) {
+    const int want = FP8 ? a.K : a.E;
+    Row<FP8, S> row(a, cb, bkey + static_cast<size_t>(w) * a.cap, beps + static_cast<size_t>(w) * a.cap, lane);
+    // error bound of a score: 4 (d + 4) units of 2^-24 of ||q||^2 + ||p||^2 + |score|
+    const float eps_c = 4.0f * static_cast<float>(d + 4) * 5.9604645e-8f;
+    const int g = lane >> 4, col = lane & 15;
+    for (int c0 = 0; c0 < n_b; c0 += kCH) {
+        if (w < kCH / 16) {  // one 16 x 16 block of the tile per wavefront
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            const int p = c0 + pb * 16 + (lane & 15);
+            const int p = c0 + w * 16 + col;
             const bool pv = p < n_b;
             if (FP8) {
                 for (int k = 0; k < d; k += 32) {
-                    const int kk = k + 8 * (lane >> 4);
                     long av, bv = 0;
-                    __builtin_memcpy(&av, Aq8 + (lane & 15) * d + kk, 8);
-                    if (pv) __builtin_memcpy(&bv, a.EV8 + (cb + p) * d + kk, 8);
+                    __builtin_memcpy(&av, Aq8 + col * d + k + 8 * g, 8);
+                    if (pv) __builtin_memcpy(&bv, a.EV8 + (cb + p) * d + k + 8 * g, 8);
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
                 }
             } else {
-                // B operand of 16 k-steps loaded before the MFMA chain that consumes it
-                for (int k0 = 0; k0 < d; k0 += 64) {
-                    float bv[16];
+                // product step s = 4 i + e takes element 16 i + 4 g + e in lane group g, so
+                // each lane reads 16 contiguous bytes of its row per four steps
+                const float4* prow = reinterpret_cast<const float4*>(a.EV + (cb + (pv ? p : 0)) * d);
+                const float4* qrow = reinterpret_cast<const float4*>(Aq + col * d);
+                const int n16 = d / 16;
+                for (int i0 = 0; i0 < n16; i0 += 8) {
+                    float4 bv[8];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int k = k0 + 4 * i;
-                        bv[i] = (pv && k < d) ? a.EV[(cb + p) * d + k + (lane >> 4)] : 0.0f;
-                    }
+                    for (int u = 0; u < 8; ++u)
+                        bv[u] = (pv && i0 + u < n16) ? prow[4 * (i0 + u) + g] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int k = k0 + 4 * i;
-                        if (k < d) {
-                            const float av = Aq[(lane & 15) * d + k + (lane >> 4)];
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[i], acc, 0, 0, 0);
+                    for (int u = 0; u < 8; ++u) {
+                        if (i0 + u < n16) {
+                            const float4 av = qrow[4 * (i0 + u) + g];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[u].x, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[u].y, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[u].z, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[u].w, acc, 0, 0, 0);
                         }
                     }
                 }
             }
+            const float pn = pv ? a.EVnorm[cb + p] : 0.0f;
+            const float ps = (FP8 && pv) ? a.EVscale[cb + p] : 1.0f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 4 * (lane >> 4) + i;
-                uint64_t key = ~0ull;
-                if (pv) {
-                    const float dot = FP8 ? acc[i] * (qs[row] * a.EVscale[cb + p]) : acc[i];
-                    const float dist = (a.metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[row] + a.EVnorm[cb + p])
-                                                                  : -dot;
-                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(p);
-                }
-                work[row * P + CH + pb * 16 + (lane & 15)] = key;
+            for (int i = 0; i < 4; ++i) {  // output element i of the lane: row 4 g + i, column col
+                const int rw = 4 * g + i;
+                const float dot = FP8 ? acc[i] * (qs[rw] * ps) : acc[i];
+                sc[rw * kCH + w * 16 + col] =
+                    (a.metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[rw] + pn) : -dot;
             }
         }
         __syncthreads();
-        // fold the chunk into the row's running list s[0, CH) (ascending): sort the chunk
-        // descending, keep the smaller of s[i] and chunk[i] (the lower half of a bitonic
-        // merge: the CH smallest of both, as a bitonic sequence), merge that ascending
-        for (int row = w; row < cntq; row += kWaves) {
-            uint64_t* srow = work + row * P;
-            bitonic_sort(srow + CH, CH, lane, true);
-            for (int i = lane; i < CH; i += 64) {
-                const uint64_t x = srow[i], y = srow[CH + i];
-                srow[i] = x < y ? x : y;
+        if (w < cntq) {
+            const float qnw = qn[w];
+            for (int h = 0; h < kCH; h += 64) {
+                const int p = c0 + h + lane;
+                const bool ok = p < n_b;
+                const float v = sc[w * kCH + h + lane];
+                const float e = (!FP8 && ok) ? eps_c * (qnw + a.EVnorm[cb + p] + fabsf(v)) : 0.0f;
+                row.offer(ok, v, e, p);
             }
-            wave_sync();
-            bitonic_merge(srow, CH, lane);
+            if (row.cnt > a.cap - kCH) {
+                row.shrink(want);
+                if (!FP8 && row.cnt > a.cap - kCH) {
+                    // (the FP8 list keeps exactly K) more near ties around the
+                    // threshold than the slack holds; decide them on exact distances now
+                    row.rescore(Aq + w * d);
+                    const uint32_t worst = row.keep_best(a.E);
+                    row.T32 = worst < row.T32 ? worst : row.T32;
+                }
+            }
         }
         __syncthreads();
     }
-
-    for (int row = w; row < cntq; row += kWaves) {
-        uint64_t* s = work + row * P;
-        // re-score the K pre-selected pivots in the direct form, keys by node id: four
-        // lanes per pivot, each over a quarter of the dimensions in float-float, combined
-        // symmetrically across the quad (so the value is the correctly rounded distance)
-        const float* qv = Aq + row * d;
-        const int per = d / 4;
-        const int sub = lane & 3;
-        for (int base = 0; base < K; base += 16) {
-            const int j = base + (lane >> 2);
-            const bool live = j < K && s[j] != ~0ull;
-            const int p = live ? static_cast<int>(s[j] & 0xFFFFFFFFu) : 0;
-            const int k0 = sub * per;  // d is a multiple of 16: per is a multiple of 4
-            const float4* pv = reinterpret_cast<const float4*>(a.EV + (cb + p) * d + k0);
-            ff32 acc{0.0f, 0.0f};
-            // the lane's quarter of the row in pieces of up to 32 floats, every load of a
-            // piece issued before its arithmetic
-            for (int seg = 0; seg < per; seg += 32) {
-                const int n4 = min(32, per - seg) / 4;
-                float4 x[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = (live && u < n4) ? pv[seg / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (u < n4) {
-                        const float* q4 = qv + k0 + seg + 4 * u;
-                        const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            if (a.metric == PA_METRIC_L2) ff_add_sqdiff(acc, q4[c], xv[c]);
-                            else ff_add_prod(acc, q4[c], xv[c]);
-                        }
-                    }
-                }
-            }
-            acc = ff_add(acc, ff32{dpp<0xB1>(acc.hi), dpp<0xB1>(acc.lo)});  // lane ^ 1
-            acc = ff_add(acc, ff32{dpp<0x4E>(acc.hi), dpp<0x4E>(acc.lo)});  // lane ^ 2
-            if (sub == 0 && j < K) {
-                uint64_t key = ~0ull;
-                if (live) {
-                    const float dist = (a.metric == PA_METRIC_L2) ? acc.hi : -acc.hi;
-                    key = (static_cast<uint64_t>(ord_f32(dist)) << 32) | static_cast<uint32_t>(a.EVid[cb + p]);
-                }
-                s[j] = key;
-            }
-        }
-        for (int j = K + lane; j < K2; j += 64) s[j] = ~0ull;
-        wave_sync();
-        bitonic_sort(s, K2, lane, false);
-        const int64_t q = qidx[row];
-        for (int e = lane; e < a.E; e += 64) {
-            int32_t id = -1;
-            float dist = __builtin_huge_valf();
-            if (e < K && s[e] != ~0ull) {
-                id = static_cast<int32_t>(s[e] & 0xFFFFFFFFu);
-                dist = unord_f32(static_cast<uint32_t>(s[e] >> 32));
-            }
-            a.out_ids[q * a.E + e] = id;
-            a.out_d[q * a.E + e] = dist;
+    if (w >= cntq) return;
+    row.shrink(want);
+    row.rescore(Aq + w * d);
+    row.keep_best(a.E);
+    row.to_node_ids();
+    // emit in (distance, node id) order: the rank of each kept key among the kept keys
+    const int n = row.cnt;
+    const int64_t q = qidx[w];
+    for (int e = n + lane; e < a.E; e += 64) {
+        a.out_ids[q * a.E + e] = -1;
+        a.out_d[q * a.E + e] = __builtin_huge_valf();
+    }
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        const uint64_t mine = i < n ? row.key[i] : ~0ull;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += row.key[j] < mine ? 1 : 0;
+        if (i < n) {
+            a.out_ids[q * a.E + rank] = static_cast<int32_t>(mine & 0xFFFFFFFFu);
+            a.out_d[q * a.E + rank] = unord_f32(static_cast<uint32_t>(mine >> 32));
         }
     }
 }
@@ -401,28 +554,43 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
                                    float* dists, int32_t* scratch_i32, hipStream_t s) {
     if (m == 0) return;
     require(r >= 1 && r <= kMaxClusters, "FES supports 1..64 clusters");
+    require(d % 16 == 0, "entry selection needs d % 16 == 0", PA_EUNSUPPORTED);
     const bool fp8 = EV8 != nullptr;
     if (fp8) require(d % 32 == 0, "FP8 entry selection needs d % 32 == 0", PA_EUNSUPPORTED);
-    if (!fp8) K = E + kRerankSlack;
     K = std::max(K, E);
+    // per-row buffer: the kept entries plus room for one chunk; FP32 form: E plus a slack
+    // for candidates whose error interval reaches the threshold
+    const int keep = fp8 ? K : E + 64;
+    const int cap = (keep + kCH + 63) / 64 * 64;
     int dev = 0, max_lds = 64 * 1024;
     PA_HIP(hipGetDevice(&dev));
     PA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    auto lds_for = [&](int P) {
-        return sizeof(float) * (kTQ * d + 2 * kTQ) + static_cast<size_t>((kTQ * d + 15) / 16) * 16 +
-               sizeof(uint64_t) * static_cast<size_t>(kTQ) * P;
-    };
-    // running list of K2 = next_pow2(K) keys per query row, and chunks of the same size
-    int K2 = 16;
-    while (K2 < K) K2 <<= 1;
-    const int CH = K2, P = 2 * K2;
-    require(lds_for(P) <= static_cast<size_t>(max_lds), "FES pre-selection list does not fit in LDS", PA_EUNSUPPORTED);
+    const size_t lds = sizeof(float) * static_cast<size_t>(kTQ) * (d + kCH) +
+                       static_cast<size_t>(kTQ) * cap * (sizeof(uint64_t) + (fp8 ? 0 : sizeof(float))) +
+                       (fp8 ? static_cast<size_t>(kTQ) * d : 0);
+    require(cap <= 16 * 64 && lds <= static_cast<size_t>(max_lds),
+            "FES candidate list of a 16-query tile does not fit in LDS", PA_EUNSUPPORTED);
     hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
     PA_HIP(hipGetLastError());
-    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, K2, CH, P, metric, scratch_i32, ids, dists};
-    const int max_tiles = static_cast<int>((m + kTQ - 1) / kTQ) + r;
-    if (fp8) hipLaunchKernelGGL(score_kernel<true>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
-    else hipLaunchKernelGGL(score_kernel<false>, dim3(max_tiles), dim3(kThreads), lds_for(P), s, a);
+    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, cap, metric, scratch_i32, ids, dists};
+    const int blocks = static_cast<int>((m + kTQ - 1) / kTQ) + r;
+    const int slots = cap / 64;
+    auto go = [&](auto fp8_tag, auto slots_tag) {
+        constexpr bool F = decltype(fp8_tag)::value;
+        constexpr int SL = decltype(slots_tag)::value;
+        hipLaunchKernelGGL((score_kernel<F, SL>), dim3(blocks), dim3(kThreads), lds, s, a);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    if (fp8) {
+        if (slots <= 4) go(T{}, std::integral_constant<int, 4>{});
+        else if (slots <= 8) go(T{}, std::integral_constant<int, 8>{});
+        else go(T{}, std::integral_constant<int, 16>{});
+    } else {
+        if (slots <= 4) go(F{}, std::integral_constant<int, 4>{});
+        else if (slots <= 8) go(F{}, std::integral_constant<int, 8>{});
+        else go(F{}, std::integral_constant<int, 16>{});
+    }
     PA_HIP(hipGetLastError());
 }
 

@@ -17,10 +17,11 @@ leaf centres through a tree: level-1 centres ~ N(0, s1^2 I), each child =
 parent + N(0, s_l^2 I), with branching ``levels`` and spreads ``spreads``; this
 gives the multi-scale cluster structure of real embedding sets, where a flat
 mixture of well separated blobs has no coarse structure at all.  Anisotropic mixtures (the
-768-dim inner-product workloads): a seeded orthonormal basis ``B`` (QR of a
-Gaussian matrix, signs fixed so diag(R) > 0) and a power-law spectrum
-``lambda_i = 1 / i``; centres ``2 B diag(sqrt(lambda)) z``, points
-``centre + B diag(sqrt(lambda)) eps``, then every point scaled to unit length.
+768-dim inner-product workloads, and the 96-dim L2 workload at 10^7-10^8 rows): a seeded
+orthonormal basis ``B`` (QR of a Gaussian matrix, signs fixed so diag(R) > 0) and a
+power-law spectrum ``lambda_i = 1 / i``; centres ``2 B diag(sqrt(lambda)) z``, points
+``centre + B diag(sqrt(lambda)) eps``, then (inner-product workloads) every point scaled
+to unit length.
 """
 
 from __future__ import annotations
@@ -53,6 +54,7 @@ class WorkloadSpec:
     n_pivots: int
     ef: tuple
     kind: str = "gmm"  # "gmm" (flat) | "hgmm" (nested) | "aniso"
+    unit_norm: bool = True  # aniso only: every point scaled to unit length
     levels: tuple = ()
     spreads: tuple = ()
     r: int = 32
@@ -90,6 +92,12 @@ SPECS = {
         queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
         sample_mode="seed_expand", n_pivots=16_384, ef=(64, 128, 256, 512),
         xr_dtypes=("f16",), kind="hgmm", levels=(16, 16, 64), spreads=(2.0, 1.0, 0.5)),
+    # the 100M x 96 L2 shape with anisotropic components (power-law spectrum, not normalised)
+    "aniso100m": WorkloadSpec(
+        name="aniso100m", config=4, n=100_000_000, dim=96, components=16_384,
+        queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
+        sample_mode="seed_expand", n_pivots=16_384, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
+        kind="aniso", unit_norm=False, xr_dtypes=("f16",)),
     "serve20m": WorkloadSpec(
         name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
         queries=100_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
@@ -139,7 +147,7 @@ def _aniso_model(seed: int, components: int, dim: int):
 
 
 def _chunk_rows(seed: int, stream_seed: int, chunk: int, n_rows: int, components: int,
-                dim: int, kind: str, model) -> np.ndarray:
+                dim: int, kind: str, model, unit_norm: bool = True) -> np.ndarray:
     rng = make_rng(stream_seed, chunk)
     comp = rng.integers(0, components, size=n_rows)
     eps = rng.standard_normal((n_rows, dim))
@@ -148,7 +156,8 @@ def _chunk_rows(seed: int, stream_seed: int, chunk: int, n_rows: int, components
     else:
         centres, scale = model
         x = centres[comp] + eps @ scale.T
-        x /= np.linalg.norm(x, axis=1, keepdims=True)
+        if unit_norm:
+            x /= np.linalg.norm(x, axis=1, keepdims=True)
     return x.astype(np.float32)
 
 
@@ -168,7 +177,7 @@ def _rows(spec: WorkloadSpec, stream_seed: int, total: int, start: int, stop: in
     def fill(c):
         lo, hi = c * CHUNK, min(total, (c + 1) * CHUNK)
         block = _chunk_rows(spec.seed, stream_seed, c, hi - lo, spec.components, spec.dim,
-                            spec.kind, model)
+                            spec.kind, model, spec.unit_norm)
         a, b = max(lo, start), min(hi, stop)
         out[a - start:b - start] = block[a - lo:b - lo]
 

@@ -152,10 +152,12 @@ def _repair(X: np.ndarray, adj: np.ndarray, medoid: int, device) -> np.ndarray:
     return _repair_with(X, adj, medoid, device, _reached_from)
 
 
-def _repair_with(X: np.ndarray, adj: np.ndarray, medoid: int, device, reached_fn) -> np.ndarray:
+def _repair_with(X: np.ndarray, adj: np.ndarray, medoid: int, device, reached_fn, nearest_fn=None) -> np.ndarray:
     """Link one node of every source strongly connected component of the unreached part
     from its nearest reached node (with a free slot); repeat until all are reached.
-    ``reached_fn(adj, start)`` gives the rows reachable from ``start`` (bool [n])."""
+    ``reached_fn(adj, start)`` gives the rows reachable from ``start`` (bool [n]);
+    ``nearest_fn(rows, allowed)`` the nearest allowed row of each given row (exact kNN by
+    default)."""
     n, R = adj.shape
     for _ in range(16):
         reached = reached_fn(adj, medoid)
@@ -178,8 +180,12 @@ def _repair_with(X: np.ndarray, adj: np.ndarray, medoid: int, device, reached_fn
         host_ok = reached & (adj < 0).any(1)
         if not host_ok.any():
             host_ok = reached
-        near, _ = exact_knn(X, X[reps], 1, "l2", device=device, candidate_mask=host_ok)
-        for u, h in zip(reps.tolist(), near[:, 0].tolist()):
+        if nearest_fn is None:
+            near, _ = exact_knn(X, X[reps], 1, "l2", device=device, candidate_mask=host_ok)
+            near = near[:, 0]
+        else:
+            near = nearest_fn(reps, host_ok)
+        for u, h in zip(reps.tolist(), near.tolist()):
             if not _append(adj, int(h), int(u)):
                 adj[int(h), -1] = u
             _append(adj, int(u), int(h))

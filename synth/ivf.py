@@ -67,7 +67,7 @@ def _nearest(x: torch.Tensor, cen: torch.Tensor) -> torch.Tensor:
 
 @torch.no_grad()
 def ivf_candidates(x32: torch.Tensor, x64: torch.Tensor, cen: torch.Tensor, assign: torch.Tensor,
-                   nprobe: int, cand: int, margin: int = 16, rows_per_gemm: int = 4096):
+                   nprobe: int, cand: int, margin: int = 16, rows_per_gemm: int = 4096, log=None):
     """Nearest ``cand`` rows of every row among its list's probe set (itself excluded):
     (ids int64 [n][cand], -1 padded; fp64 distances [n][cand], +inf padded), rows ordered
     by (distance, id)."""
@@ -93,6 +93,8 @@ def ivf_candidates(x32: torch.Tensor, x64: torch.Tensor, cen: torch.Tensor, assi
     out_d = torch.full((n, cand), float("inf"), dtype=torch.float64, device=dev)
     starts_h, counts_h = starts.cpu().numpy(), counts.cpu().numpy()
     for c in range(L):
+        if log is not None and c % 8192 == 0 and c:
+            log(f"ivf: candidates of {c} of {L} lists")
         if counts_h[c] == 0:
             continue
         probe = torch.cat([order[starts_h[p]:starts_h[p] + counts_h[p]] for p in probes[c]])
@@ -157,25 +159,49 @@ def build_graph_ivf(X: np.ndarray, R: int, *, n_lists: int | None = None, nprobe
     cen, assign = coarse_kmeans(x32, L, seed)
     say(f"ivf: {L} lists over {n} rows in {time.time() - t:.1f}s")
     t = time.time()
-    ci, cd = ivf_candidates(x32, x64, cen, assign, nprobe, cand)
+    ci, cd = ivf_candidates(x32, x64, cen, assign, nprobe, cand, log=say)
     del assign
     say(f"ivf: {cand} candidates per row from {min(nprobe, L)} lists in {time.time() - t:.1f}s")
     t = time.time()
     fwd = rng_prune(x64, ci, cd, R)
     del ci, cd
+    say(f"ivf: forward lists pruned in {time.time() - t:.1f}s")
     full = add_reverse(x64, fwd, R)
     del fwd
     say(f"ivf: pruned, reverse edges added in {time.time() - t:.1f}s")
-    del x32, x64
+    del x64
     if dev.type == "cuda":
         torch.cuda.empty_cache()
     t = time.time()
     adj = _sort_rows(X, full.cpu().numpy(), dev)
     del full
     if repair:
+        xn = (x32.double() ** 2).sum(1)
+
+        def nearest(rows, allowed):
+            # nearest allowed row by the direct fp64 distance among the 64 best of an fp32
+            # scan (ties by id), with the vectors already on the device
+            ok = torch.as_tensor(allowed).to(dev)
+            q = x32[torch.as_tensor(rows).to(dev)]
+            out = []
+            blk = max(1, min(256, (1 << 30) // (8 * n)))  # ~1 GiB of scores per block
+            for a in range(0, q.shape[0], blk):
+                qa = q[a:a + blk]
+                sc = (xn[None, :] - 2.0 * (qa.double() @ x32.double().T)).float() if n <= 1 << 20 else \
+                    xn.float()[None, :] - 2.0 * (qa @ x32.T)
+                sc[:, ~ok] = float("inf")
+                _, cand = torch.topk(sc, min(64, n), dim=1, largest=False)
+                d = ((x32[cand].double() - qa.double()[:, None, :]) ** 2).sum(-1)
+                d = torch.where(ok[cand], d, torch.full_like(d, float("inf")))
+                key_id = torch.argsort(cand, dim=1, stable=True)
+                cand, d = torch.gather(cand, 1, key_id), torch.gather(d, 1, key_id)
+                out.append(torch.gather(cand, 1, torch.argsort(d, dim=1, stable=True)[:, :1])[:, 0])
+            return torch.cat(out).cpu().numpy()
+
         adj = _repair_with(X, adj, medoid_of(X), dev,
-                           lambda a, s: reached_gpu(torch.as_tensor(a).to(dev), s).cpu().numpy())
+                           lambda a, s: reached_gpu(torch.as_tensor(a).to(dev), s).cpu().numpy(), nearest)
         adj = _sort_rows(X, adj, dev)
+    del x32
     say(f"ivf: rows ordered, connected from the medoid in {time.time() - t:.1f}s")
     return adj.astype(np.int32)
 

@@ -62,3 +62,17 @@ def test_breadth_first_reachability_on_a_hand_built_graph():
     adj = torch.tensor([[1, -1], [2, -1], [0, 1], [4, -1], [-1, -1]])
     assert reached_gpu(adj, 0).tolist() == [True, True, True, False, False]
     assert reached_gpu(adj, 3).tolist() == [False, False, False, True, True]
+
+
+def test_repair_path_matches_the_exact_builder():
+    # degree 3 on well separated blobs leaves parts unreachable until the repair links them
+    from synth.graph import _reached_from, add_reverse, rng_prune
+    X = gmm_points(11, 2000, 8, 40)
+    x64 = torch.as_tensor(X).double()
+    ids, d = exact_knn(X, None, 3, "l2", device="cpu", exclude_self=True)
+    raw = add_reverse(x64, rng_prune(x64, torch.as_tensor(ids), torch.as_tensor(d), 3), 3).numpy()
+    assert not _reached_from(raw, medoid_of(X)).all()
+    exact = build_graph(X, 3, device="cpu")
+    ivf = build_graph_ivf(X, 3, n_lists=4, nprobe=4, device="cpu")
+    assert (exact == ivf).all()
+    assert reached_gpu(torch.as_tensor(ivf).long(), medoid_of(X)).all()
