@@ -78,7 +78,29 @@ def large(spec):
     return spec.n >= 4_000_000
 
 
-def build_fixture(spec, device, cache=None, nprobe=8):
+def check_ground_truth(X, Q, gt, spec, device, n=64):
+    """Recomputes the first n queries' top k one query at a time (fp64 distances over every
+    row, ties by id) and stops the run if any differs from the batched ground truth."""
+    import torch
+    x = torch.as_tensor(X).to(device)
+    bad = 0
+    for i in range(min(n, Q.shape[0])):
+        q = torch.as_tensor(Q[i]).to(device).double()
+        d = torch.empty(x.shape[0], dtype=torch.float64, device=device)
+        for a in range(0, x.shape[0], 1 << 22):
+            xa = x[a:a + (1 << 22)].double()
+            d[a:a + (1 << 22)] = ((xa - q) ** 2).sum(1) if spec.metric == "l2" else -(xa @ q)
+        top = torch.topk(d, spec.k + 16, largest=False).indices
+        dd = d[top]
+        order = sorted(range(top.shape[0]), key=lambda j: (float(dd[j]), int(top[j])))
+        ref = [int(top[j]) for j in order[:spec.k]]
+        bad += int(ref != [int(v) for v in gt[i][:spec.k]])
+    log(f"ground truth re-derived for {min(n, Q.shape[0])} queries one at a time: {bad} differ")
+    if bad:
+        raise RuntimeError(f"batched ground truth differs from the per-query recomputation on {bad} queries")
+
+
+def build_fixture(spec, device, cache=None, nprobe=64):
     """Base set, queries, full graph and ground truth.  The graph of a large workload comes
     from the IVF-restricted builder; ``cache`` (a directory) keeps the graph, the ground
     truth and the subgraph between runs (the vectors are regenerated from their seeds)."""
@@ -106,6 +128,8 @@ def build_fixture(spec, device, cache=None, nprobe=8):
         gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device,
                           budget_bytes=(32 << 30) if large(spec) else None)
         log(f"ground truth in {time.time() - t:.1f}s")
+        if large(spec):
+            check_ground_truth(X, Q, gt, spec, device)
         if cache:
             os.makedirs(cache, exist_ok=True)
             np.save(path("adj"), adj)
@@ -689,6 +713,15 @@ def cpu_baseline(spec, fx, shared, ef_pair, budget_s, plain_ef=None):
     return out
 
 
+def serve_batch_bytes(spec, m, ef):
+    """Device bytes of a serving micro-batch of m requests at list size ef (the footprint the
+    server's admission charges, from the header's formula)."""
+    al = lambda b: (b + 255) // 256 * 256
+    e = min(ef, spec.n_pivots // spec.r)
+    return (al(4 * m * spec.dim) + al(4 * m * spec.d_r) + al(4 * m) + 2 * al(4 * m * e) + 2 * al(4 * m * ef)
+            + al(16 * m) + al(4 * m) + al(4 * (3 * spec.r + 2 + m)))
+
+
 def serve_bench(idx, spec, fx, rates, seconds, budget):
     """Open-loop Poisson arrivals at each rate; latency from the scheduled arrival time.
 
@@ -795,7 +828,7 @@ def main():
     ap.add_argument("--n", type=int, default=0,
                     help="base rows (the first n rows of the workload's base set; 0: all of them)")
     ap.add_argument("--queries", type=int, default=0, help="queries (the first ones; 0: the workload's count)")
-    ap.add_argument("--nprobe", type=int, default=8, help="IVF lists probed per row by the large-N graph builder")
+    ap.add_argument("--nprobe", type=int, default=64, help="IVF lists probed per row by the large-N graph builder")
     ap.add_argument("--fixture-cache", default="",
                     help="directory that keeps the graph, ground truth and subgraph between runs")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-form distance-error leg")
@@ -915,7 +948,16 @@ def main():
             extra["memory_bounded"] = memory_leg(spec, fx, shared, ef, idx.info(), max(1, min(args.steps, 3)))
         if form == "f16" and args.serve_rates:
             rates = [float(x) for x in args.serve_rates.split(",") if x]
-            serving = serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)
+            serving = {"index_hbm_bytes": idx.info()["hbm_bytes"],
+                       "rates": serve_bench(idx, spec, fx, rates, args.serve_seconds, args.serve_budget)}
+            # a budget that binds: the index plus three slots of 32 requests at list size 512
+            tight = serving["index_hbm_bytes"] + 3 * serve_batch_bytes(spec, 32, 512)
+            low = [r for r in rates if r <= 20000][-2:]
+            log(f"serving under a binding budget of {tight} bytes")
+            serving["binding_budget"] = {
+                "hbm_budget": tight,
+                "what": "index bytes + 3 slots holding 32 requests at ef 512 each (more at smaller ef)",
+                "rates": serve_bench(idx, spec, fx, low, args.serve_seconds, tight)}
         idx.close()
     if args.flat and not args.no_extra and args.workload + "_flat" in SPECS and not args.n:
         log("flat mixture (centres ~ N(0, 4I)) at the same shape")
@@ -951,7 +993,7 @@ def main():
     if serving is not None:
         out["serving"] = {"workload": f"{spec.name} index, fp16 reduced vectors; Poisson arrivals, k in "
                                       f"{{10,50,100}}, ef in {{64,128,256,512}}, {args.serve_seconds}s per rate, "
-                                      f"HBM budget {args.serve_budget} B", "rates": serving}
+                                      f"HBM budget {args.serve_budget} B (index + slot arenas)", **serving}
     if not args.no_cpu_baseline:
         plain_ef = baseline_cpu_only.get("ef") if baseline_cpu_only else f["ef_cpu"]
         out["cpu_baseline"] = cpu_baseline(spec, fx, shared, (f["ef_gpu"], f["ef_cpu"]), args.cpu_budget, plain_ef)

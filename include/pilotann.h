@@ -526,19 +526,27 @@ pa_status pa_search(pa_index* idx, const float* Q_host, int64_t m, int32_t k,
 /* ------------------------------------------------------------ serving loop */
 
 /* Continuous batching over an index (the serving form of the search; the paper batches
- * and pipelines queries, section 4.2).  Requests of uneven k and ef are queued in arrival
- * order; a scheduler admits the head of the queue into a micro-batch while the device
- * state of all admitted, unfinished requests fits hbm_budget bytes (a request holds
- * 4*dim + 4*d_r + 8*min(ef, n/r) + 8*ef + 24 bytes) and one of `streams` micro-batch slots is
- * free; projection, routing, entry selection and stage 1 of a micro-batch run on its slot's
- * stream, so several micro-batches overlap on the GPU, and stage-1 lists stay in HBM until
- * the hand-off.  Stages 2-3 run on host threads with ef_cpu = ef.  Each request's result
- * is the same whatever else is in flight.  The index must outlive the server and must not
- * be rebuilt while it runs; pa_search on the same index may run concurrently. */
+ * and pipelines queries, section 4.2).  hbm_budget bounds the device memory of the index
+ * and the server together: the index's own tables (pa_index_get_info hbm_bytes at create)
+ * come first, and what remains is split into `streams` micro-batch slots, each with one
+ * device arena of min((hbm_budget - index bytes) / streams, the bytes of a full micro-batch
+ * at list size 512) allocated at create.  Requests of uneven k and ef are queued in arrival
+ * order; when a slot is free the scheduler takes the head of the queue into its
+ * micro-batch while the batch's real footprint fits the arena: for m requests whose
+ * largest list size is f, with e = min(f, n_p / r), the sum of
+ *   4 m dim, 4 m d_r, 4 m, 4 m e (twice), 4 m f (twice), 16 m, 4 m, 4 (3 r + 2 + m)
+ * bytes, each rounded up to 256 (queries, reduced queries, clusters, entries, stage-1
+ * lists, counters, list sizes, entry-selection scratch).  Projection, routing, entry
+ * selection and stage 1 of a micro-batch run on its slot's stream, so several
+ * micro-batches overlap on the GPU, and stage-1 lists stay in HBM until the hand-off.
+ * Stages 2-3 run on host threads with ef_cpu = ef.  Each request's result is the same
+ * whatever else is in flight.  The index must outlive the server and must not be rebuilt
+ * while it runs; pa_search on the same index may run concurrently (its buffers are not
+ * covered by the server's budget). */
 typedef struct pa_server pa_server;
 
 typedef struct {
-    int64_t hbm_budget;  /* bytes of request state in flight on the device (> 0)        */
+    int64_t hbm_budget;  /* device bytes of the index plus the server's slots (> 0)     */
     int32_t max_batch;   /* requests per micro-batch (0: 1024)                          */
     int32_t streams;     /* micro-batch slots / GPU streams (0: 2)                      */
     int32_t threads;     /* host threads for stages 2-3 (0: index default)             */
@@ -553,13 +561,15 @@ typedef struct {
     double t_done_us;    /* when its result was published                                */
 } pa_result_info;
 
-/* Start the scheduler and completion threads; allocates `streams` slots of max_batch
- * requests in HBM and pinned host memory up front (none later). */
+/* Start the scheduler and completion threads; allocates the slots' device arenas and
+ * pinned host buffers for max_batch requests up front (none later).  PA_EHBM if the budget
+ * cannot hold the index and one request of list size 512 per slot. */
 pa_status pa_server_create(pa_index* idx, const pa_server_params* params, pa_server** out);
 
 /* Queue one query q_host [dim] fp32 (copied) with its k and ef.  Never blocks and never
- * rejects for lack of budget: the request waits in the queue.  PA_EINVAL for k or ef out of
- * range, PA_EHBM if the request alone exceeds the budget, PA_ESTATE after a failure. */
+ * rejects for lack of budget: the request waits in the queue (every request fits a slot
+ * alone, as create checked).  PA_EINVAL for k or ef out of range, PA_ENONFINITE for a
+ * non-finite query, PA_ESTATE after a failure. */
 pa_status pa_server_submit(pa_server* s, const float* q_host, int32_t k, int32_t ef, uint64_t tag);
 
 /* Non-blocking: move up to max_results finished requests out.  info [max_results];

@@ -291,7 +291,7 @@ extern "C" {
 
 const char* pa_last_error(void) { return g_last_error.c_str(); }
 
-int32_t pa_abi_version(void) { return 11; }
+int32_t pa_abi_version(void) { return 12; }
 
 pa_status pa_device_init(int32_t device) {
     return guarded([&] {

@@ -34,6 +34,10 @@ __device__ __forceinline__ uint32_t ord_f32(float f) {
 __device__ __forceinline__ float unord_f32(uint32_t u) {
     return __uint_as_float((u & 0x80000000u) ? (u ^ 0x80000000u) : ~u);
 }
+__device__ __forceinline__ int mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+}
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -41,20 +45,31 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // scratch (int32): [0, r) counts | [r, 2r+1) offsets | [2r+1, 3r+2) tile prefix | perm[m]
+// One block; every wavefront aggregates its 64 queries per cluster with ballots, so the
+// shared counters see one atomic per (wavefront, cluster) present instead of one per query.
 __global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__ cluster, int64_t m, int r,
                                                      int32_t* __restrict__ scratch) {
     __shared__ int cnt[kMaxClusters];
     __shared__ int cur[kMaxClusters];
     __shared__ int off[kMaxClusters + 1];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63;
     if (t < kMaxClusters) {
         cnt[t] = 0;
         cur[t] = 0;
     }
     __syncthreads();
-    for (int64_t i = t; i < m; i += 1024) {
-        const int c = cluster[i];
-        if (c >= 0 && c < r) atomicAdd(&cnt[c], 1);
+    for (int64_t i0 = t - lane; i0 < m; i0 += 1024) {
+        const int64_t i = i0 + lane;
+        int c = i < m ? cluster[i] : -1;
+        if (c < 0 || c >= r) c = -1;
+        uint64_t todo = __ballot(c >= 0);
+        while (todo) {
+            const int lead = __builtin_ctzll(todo);
+            const int cc = __builtin_amdgcn_readlane(c, lead);
+            const uint64_t same = __ballot(c == cc);
+            if (lane == lead) atomicAdd(&cnt[cc], __popcll(same));
+            todo &= ~same;
+        }
     }
     __syncthreads();
     if (t == 0) {
@@ -73,9 +88,21 @@ __global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__
     }
     __syncthreads();
     int32_t* perm = scratch + 3 * r + 2;
-    for (int64_t i = t; i < m; i += 1024) {
-        const int c = cluster[i];
-        if (c >= 0 && c < r) perm[off[c] + atomicAdd(&cur[c], 1)] = static_cast<int32_t>(i);
+    for (int64_t i0 = t - lane; i0 < m; i0 += 1024) {
+        const int64_t i = i0 + lane;
+        int c = i < m ? cluster[i] : -1;
+        if (c < 0 || c >= r) c = -1;
+        uint64_t todo = __ballot(c >= 0);
+        while (todo) {
+            const int lead = __builtin_ctzll(todo);
+            const int cc = __builtin_amdgcn_readlane(c, lead);
+            const uint64_t same = __ballot(c == cc);
+            int base = 0;
+            if (lane == lead) base = atomicAdd(&cur[cc], __popcll(same));
+            base = __builtin_amdgcn_readlane(base, lead);
+            if (c == cc) perm[off[cc] + base + mbcnt(same)] = static_cast<int32_t>(i);
+            todo &= ~same;
+        }
     }
 }
 
@@ -148,10 +175,6 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __builtin_bit_cast(float,
                               __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ int mbcnt(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
 }
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -278,9 +301,9 @@ struct Row {
     // dimensions in float-float (pieces of up to 32 elements, all loads of a piece issued
     // before its arithmetic), combined symmetrically across the quad, so the value is the
     // correctly rounded distance whatever the summation order.  Sixteen pivots per pass.
-    __device__ void rescore(const float* qv) {
+    __device__ void rescore(const float* qv, bool node_ids = false, int from = 0) {
         const int d = a.d, per = d / 4, sub = lane & 3;
-        for (int base = 0; base < cnt; base += 16) {
+        for (int base = from; base < cnt; base += 16) {
             const int t = base + (lane >> 2);
             const bool live = t < cnt;
             const int pos = live ? static_cast<int>(key[t] & 0xFFFFFFFFu) : 0;
@@ -308,7 +331,8 @@ struct Row {
             acc = ff_add(acc, ff32{dpp<0x4E>(acc.hi), dpp<0x4E>(acc.lo)});  // lane ^ 2
             const float v = (a.metric == PA_METRIC_L2) ? acc.hi : -acc.hi;
             if (live && sub == 0) {
-                key[t] = (static_cast<uint64_t>(ord_f32(v)) << 32) | static_cast<uint32_t>(pos);
+                const uint32_t low = node_ids ? static_cast<uint32_t>(a.EVid[cb + pos]) : static_cast<uint32_t>(pos);
+                key[t] = (static_cast<uint64_t>(ord_f32(v)) << 32) | low;
                 if (!FP8) eps[t] = 0.0f;
             }
         }
@@ -317,7 +341,8 @@ struct Row {
 
     // Exact values: keeps the best `want` by (distance, node id) (distinct: the node ids of
     // a bucket are distinct).  Returns the largest kept distance's ordered encoding.
-    __device__ uint32_t keep_best(int want) {
+    // With node_ids the keys already carry node ids in their low bits.
+    __device__ uint32_t keep_best(int want, bool node_ids = false) {
         const int slots = (cnt + 63) / 64;
         uint64_t kk[S], nk[S];
         float ee[S];
@@ -325,9 +350,10 @@ struct Row {
         load(kk, ee, ok, slots);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            nk[i] = ok[i] ? ((kk[i] & 0xFFFFFFFF00000000ull) |
-                             static_cast<uint32_t>(a.EVid[cb + static_cast<int64_t>(kk[i] & 0xFFFFFFFFu)]))
-                          : ~0ull;
+            nk[i] = !ok[i] ? ~0ull
+                           : node_ids ? kk[i]
+                                      : ((kk[i] & 0xFFFFFFFF00000000ull) |
+                                         static_cast<uint32_t>(a.EVid[cb + static_cast<int64_t>(kk[i] & 0xFFFFFFFFu)]));
         const uint64_t t = cnt > want ? kth_smallest<uint64_t, 64, S>(nk, ok, slots, want) : ~0ull;
 #pragma unroll
         for (int i = 0; i < S; ++i) keep[i] = ok[i] && nk[i] <= t;
@@ -335,16 +361,12 @@ struct Row {
         return static_cast<uint32_t>(t >> 32);
     }
 
-    // Rewrites the (exact) entries as (ordered distance << 32) | node id.
-    __device__ void to_node_ids() {
-        for (int t = lane; t < cnt; t += 64)
-            key[t] = (key[t] & 0xFFFFFFFF00000000ull) |
-                     static_cast<uint32_t>(a.EVid[cb + static_cast<int64_t>(key[t] & 0xFFFFFFFFu)]);
-        wave_sync();
-    }
 };
 
-template <bool FP8, int S>
+// SL > 0: the row's n_b <= 64 SL scores stay in registers (SL per lane) and one selection
+// runs after the last chunk; SL == 0: the candidate list in LDS is shrunk as chunks arrive
+// (any bucket size).
+template <bool FP8, int S, int SL>
 __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int d = a.d;
@@ -419,7 +441,11 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     // error bound of a score: 4 (d + 4) units of 2^-24 of ||q||^2 + ||p||^2 + |score|
     const float eps_c = 4.0f * static_cast<float>(d + 4) * 5.9604645e-8f;
     const int g = lane >> 4, col = lane & 15;
-    for (int c0 = 0; c0 < n_b; c0 += kCH) {
+    float sv[SL > 0 ? SL : 1], se[SL > 0 ? SL : 1];  // register path: the row's scores and bounds
+#pragma unroll
+    for (int ci = 0; ci < (SL > 0 ? SL / 2 : 1 << 30); ++ci) {
+        const int c0 = ci * kCH;
+        if (c0 >= n_b) break;
         if (w < kCH / 16) {  // one 16 x 16 block of the tile per wavefront
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int p = c0 + w * 16 + col;
@@ -465,13 +491,29 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
             }
         }
         __syncthreads();
-        if (w < cntq) {
+        if constexpr (SL > 0) {
+            if (w < cntq) {
+#pragma unroll
+                for (int h = 0; h < kCH / 64; ++h) {
+                    const int p = c0 + 64 * h + lane;
+                    sv[2 * ci + h] = sc[w * kCH + 64 * h + lane];
+                    se[2 * ci + h] = (!FP8 && p < n_b) ? a.EVnorm[cb + p] : 0.0f;  // the norm, for now
+                }
+            }
+        } else if (w < cntq) {
             const float qnw = qn[w];
-            for (int h = 0; h < kCH; h += 64) {
-                const int p = c0 + h + lane;
+            float pn[kCH / 64];
+#pragma unroll
+            for (int h = 0; h < kCH / 64; ++h) {  // all norm loads in flight before the offers
+                const int p = c0 + 64 * h + lane;
+                pn[h] = (!FP8 && p < n_b) ? a.EVnorm[cb + p] : 0.0f;
+            }
+#pragma unroll
+            for (int h = 0; h < kCH / 64; ++h) {
+                const int p = c0 + 64 * h + lane;
                 const bool ok = p < n_b;
-                const float v = sc[w * kCH + h + lane];
-                const float e = (!FP8 && ok) ? eps_c * (qnw + a.EVnorm[cb + p] + fabsf(v)) : 0.0f;
+                const float v = sc[w * kCH + 64 * h + lane];
+                const float e = (!FP8 && ok) ? eps_c * (qnw + pn[h] + fabsf(v)) : 0.0f;
                 row.offer(ok, v, e, p);
             }
             if (row.cnt > a.cap - kCH) {
@@ -488,10 +530,75 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
         __syncthreads();
     }
     if (w >= cntq) return;
-    row.shrink(want);
-    row.rescore(Aq + w * d);
-    row.keep_best(a.E);
-    row.to_node_ids();
+    if constexpr (SL > 0) {
+        // one selection over the row's scores (position of slot i, lane l: 64 i + l)
+        const int used = (n_b + 63) / 64;
+        uint32_t key[SL];
+        bool ok[SL];
+        int valid = 0;
+#pragma unroll
+        for (int i = 0; i < SL; ++i) {
+            ok[i] = i < used && 64 * i + lane < n_b;
+            valid += __popcll(__ballot(ok[i]));
+        }
+        if (FP8) {
+            // the K best by (score, position): every score below the K-th smallest, and of
+            // the scores equal to it the ones at the lowest positions
+            const int k = min(a.K, valid);
+#pragma unroll
+            for (int i = 0; i < SL; ++i) key[i] = ok[i] ? ord_f32(sv[i]) : 0xFFFFFFFFu;
+            const uint32_t T = kth_smallest<uint32_t, 32, SL>(key, ok, used, k);
+            int below = 0;
+#pragma unroll
+            for (int i = 0; i < SL; ++i)
+                if (i < used) below += __popcll(__ballot(ok[i] && key[i] < T));
+            int ties = 0;
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                if (i < used) {
+                    const bool tie = ok[i] && key[i] == T;
+                    const uint64_t tm = __ballot(tie);
+                    const bool in = ok[i] && (key[i] < T || (tie && ties + mbcnt(tm) < k - below));
+                    ties += __popcll(tm);
+                    const uint64_t m = __ballot(in);
+                    if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(key[i]) << 32) | (64 * i + lane);
+                    row.cnt += __popcll(m);
+                }
+            }
+            wave_sync();
+            row.rescore(Aq + w * d, true);
+        } else {
+            // drop the scores whose lower end exceeds the E-th smallest upper end
+            const float qnw = qn[w];
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                se[i] = eps_c * (qnw + se[i] + fabsf(sv[i]));
+                key[i] = !ok[i] ? 0xFFFFFFFFu : (Row<FP8, S>::finite(sv[i]) ? Row<FP8, S>::hi_ord(sv[i], se[i]) : 0xFFFFFFFFu);
+            }
+            const uint32_t T = valid > a.E ? kth_smallest<uint32_t, 32, SL>(key, ok, used, a.E) : 0xFFFFFFFFu;
+            int exact = 0;  // entries [0, exact) of the list are already exact
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                if (i < used) {
+                    const bool in = ok[i] && (!Row<FP8, S>::finite(sv[i]) || Row<FP8, S>::lo_ord(sv[i], se[i]) <= T);
+                    const uint64_t m = __ballot(in);
+                    if (row.cnt + __popcll(m) > a.cap) {  // near ties beyond the slack: decide a batch
+                        row.rescore(Aq + w * d, true, exact);
+                        row.keep_best(a.E, true);
+                        exact = row.cnt;
+                    }
+                    if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(ord_f32(sv[i])) << 32) | (64 * i + lane);
+                    row.cnt += __popcll(m);
+                }
+            }
+            wave_sync();
+            row.rescore(Aq + w * d, true, exact);
+        }
+    } else {
+        row.shrink(want);
+        row.rescore(Aq + w * d, true);
+    }
+    row.keep_best(a.E, true);
     // emit in (distance, node id) order: the rank of each kept key among the kept keys
     const int n = row.cnt;
     const int64_t q = qidx[w];
@@ -558,10 +665,19 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     const bool fp8 = EV8 != nullptr;
     if (fp8) require(d % 32 == 0, "FP8 entry selection needs d % 32 == 0", PA_EUNSUPPORTED);
     K = std::max(K, E);
-    // per-row buffer: the kept entries plus room for one chunk; FP32 form: E plus a slack
-    // for candidates whose error interval reaches the threshold
+    // registers for the scores of buckets that span several chunks, up to 2,048 pivots
+    // (FP8) or 1,024 (FP32: scores and their bounds); a bucket of one chunk gains nothing
+    // from them (its list is shrunk once either way) and keeps the smaller register
+    // footprint of the list path, which leaves room for two blocks per CU
+    const int need = (n_b + 63) / 64;
+    int sl = 0;
+    if (fp8) sl = need <= 2 ? 0 : (need <= 8 ? 8 : (need <= 32 ? 32 : 0));
+    else sl = need <= 2 ? 0 : (need <= 8 ? 8 : (need <= 16 ? 16 : 0));
+    // per-row list: the kept entries (FP32 form: E plus a slack of 64 for candidates whose
+    // error interval reaches the threshold), and with the scores not in registers room for
+    // one more chunk
     const int keep = fp8 ? K : E + 64;
-    const int cap = (keep + kCH + 63) / 64 * 64;
+    const int cap = (keep + (sl > 0 ? 0 : kCH) + 63) / 64 * 64;
     int dev = 0, max_lds = 64 * 1024;
     PA_HIP(hipGetDevice(&dev));
     PA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -575,22 +691,31 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, cap, metric, scratch_i32, ids, dists};
     const int blocks = static_cast<int>((m + kTQ - 1) / kTQ) + r;
     const int slots = cap / 64;
-    auto go = [&](auto fp8_tag, auto slots_tag) {
+    auto go = [&](auto fp8_tag, auto s_tag, auto sl_tag) {
         constexpr bool F = decltype(fp8_tag)::value;
-        constexpr int SL = decltype(slots_tag)::value;
-        hipLaunchKernelGGL((score_kernel<F, SL>), dim3(blocks), dim3(kThreads), lds, s, a);
+        constexpr int S_ = decltype(s_tag)::value;
+        constexpr int SL_ = decltype(sl_tag)::value;
+        hipLaunchKernelGGL((score_kernel<F, S_, SL_>), dim3(blocks), dim3(kThreads), lds, s, a);
     };
-    using T = std::true_type;
-    using F = std::false_type;
-    if (fp8) {
-        if (slots <= 4) go(T{}, std::integral_constant<int, 4>{});
-        else if (slots <= 8) go(T{}, std::integral_constant<int, 8>{});
-        else go(T{}, std::integral_constant<int, 16>{});
-    } else {
-        if (slots <= 4) go(F{}, std::integral_constant<int, 4>{});
-        else if (slots <= 8) go(F{}, std::integral_constant<int, 8>{});
-        else go(F{}, std::integral_constant<int, 16>{});
-    }
+    auto by_sl = [&](auto fp8_tag, auto s_tag) {
+        using I = std::integral_constant<int, 0>;
+        if (decltype(fp8_tag)::value) {
+            if (sl == 8) go(fp8_tag, s_tag, std::integral_constant<int, 8>{});
+            else if (sl == 32) go(fp8_tag, s_tag, std::integral_constant<int, 32>{});
+            else go(fp8_tag, s_tag, I{});
+        } else {
+            if (sl == 8) go(fp8_tag, s_tag, std::integral_constant<int, 8>{});
+            else if (sl == 16) go(fp8_tag, s_tag, std::integral_constant<int, 16>{});
+            else go(fp8_tag, s_tag, I{});
+        }
+    };
+    auto by_s = [&](auto fp8_tag) {
+        if (slots <= 4) by_sl(fp8_tag, std::integral_constant<int, 4>{});
+        else if (slots <= 8) by_sl(fp8_tag, std::integral_constant<int, 8>{});
+        else by_sl(fp8_tag, std::integral_constant<int, 16>{});
+    };
+    if (fp8) by_s(std::true_type{});
+    else by_s(std::false_type{});
     PA_HIP(hipGetLastError());
 }
 

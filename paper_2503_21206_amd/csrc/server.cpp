@@ -1,6 +1,7 @@
 // Serving loop: continuous batching of single-query requests of uneven k and ef over an
-// index.  A scheduler thread admits queued requests in arrival order while the device
-// state of the requests in flight fits the HBM budget and a micro-batch slot is free,
+// index.  The HBM budget covers the index's own tables and the slots' device arenas; a
+// scheduler thread takes queued requests in arrival order into a free slot while the
+// micro-batch's real device footprint (at its largest list size) fits the slot's arena,
 // and enqueues projection, routing, entry selection and stage 1 for the micro-batch on
 // that slot's stream (several slots overlap on the GPU).  A completion thread waits for
 // each micro-batch in admission order, runs stages 2-3 for its requests on the host pool
@@ -30,7 +31,6 @@ struct Request {
     std::vector<float> q;
     int k = 0, ef = 0;
     uint64_t tag = 0;
-    int64_t bytes = 0;
     double t_submit = 0, t_admit = 0;
 };
 
@@ -40,10 +40,14 @@ struct Result {
     std::vector<float> d;
 };
 
+// One micro-batch slot: a stream and a device arena that is carved, per micro-batch, into
+// the buffers of its m requests at the batch's largest list size ef_max.
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    DevBuf q, qr, cl, eid, ed, bid, bd, cnt, efq, scr;
+    DevBuf arena;
+    void *q = nullptr, *qr = nullptr, *cl = nullptr, *eid = nullptr, *ed = nullptr, *bid = nullptr, *bd = nullptr,
+         *cnt = nullptr, *efq = nullptr, *scr = nullptr;
     PinBuf q_pin, beam_pin, efq_pin;
     std::vector<Request> reqs;
     int ef_max = 0;
@@ -64,6 +68,7 @@ struct pa_server {
     std::deque<pa::Result> done;
     int64_t submitted = 0, completed = 0;
     int64_t bytes_in_flight = 0;
+    int64_t arena_bytes = 0;  // device bytes of each slot's arena
     int64_t max_batch_seen = 0, batches = 0;
     std::string error;
     pa_status error_code = PA_OK;
@@ -85,11 +90,41 @@ double now_us(const pa_server* s) {
 
 int entries_for(const pa_index* idx, int ef) { return std::min(ef, idx->n_b); }
 
-// Device bytes a request holds while in flight (query, reduced query, cluster, entries,
-// stage-1 list, counters, list size).
-int64_t request_bytes(const pa_index* idx, int ef) {
-    const int64_t D = idx->p.dim, d_r = idx->p.d_r;
-    return 4 * D + 4 * d_r + 4 + 8 * entries_for(idx, ef) + 8 * ef + 16 + 4;
+constexpr int64_t kAlign = 256;
+int64_t aligned(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// Device bytes of a micro-batch of m requests whose largest list size is ef: the queries,
+// reduced queries, clusters, entries (ids and distances), stage-1 lists (ids and
+// distances) and counters at stride ef, the per-query list sizes and the entry-selection
+// scratch, each buffer rounded up to 256 bytes.
+int64_t batch_bytes(const pa_index* idx, int64_t m, int ef) {
+    const int64_t D = idx->p.dim, d_r = idx->p.d_r, E = entries_for(idx, ef);
+    return aligned(4 * m * D) + aligned(4 * m * d_r) + aligned(4 * m) + 2 * aligned(4 * m * E) +
+           2 * aligned(4 * m * ef) + aligned(16 * m) + aligned(4 * m) +
+           aligned(4 * static_cast<int64_t>(select_entries_scratch_ints(m, idx->p.r)));
+}
+
+// Points the slot's buffers into its arena for m requests at stride ef.
+void carve(const pa_index* idx, Slot& sl, int64_t m, int ef) {
+    const int64_t D = idx->p.dim, d_r = idx->p.d_r, E = entries_for(idx, ef);
+    auto* base = static_cast<char*>(sl.arena.p);
+    int64_t off = 0;
+    auto take = [&](int64_t b) {
+        void* p = base + off;
+        off += aligned(b);
+        return p;
+    };
+    sl.q = take(4 * m * D);
+    sl.qr = take(4 * m * d_r);
+    sl.cl = take(4 * m);
+    sl.eid = take(4 * m * E);
+    sl.ed = take(4 * m * E);
+    sl.bid = take(4 * m * ef);
+    sl.bd = take(4 * m * ef);
+    sl.cnt = take(16 * m);
+    sl.efq = take(4 * m);
+    sl.scr = take(4 * static_cast<int64_t>(select_entries_scratch_ints(m, idx->p.r)));
+    require(off <= static_cast<int64_t>(sl.arena.bytes), "micro-batch exceeds its slot", PA_EINTERNAL);
 }
 
 void fail_all(pa_server* s, pa_status code, const std::string& msg) {
@@ -116,21 +151,20 @@ void launch_slot(pa_server* s, Slot& sl) {
         std::memcpy(qp + i * D, sl.reqs[i].q.data(), sizeof(float) * D);
         ep[i] = sl.reqs[i].ef;
     }
+    carve(idx, sl, m, ef);
     hipStream_t st = sl.stream;
-    PA_HIP(hipMemcpyAsync(sl.q.p, qp, sizeof(float) * m * D, hipMemcpyHostToDevice, st));
-    PA_HIP(hipMemcpyAsync(sl.efq.p, ep, sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
-    launch_project(static_cast<const float*>(sl.q.p), m, D, static_cast<const float*>(idx->V_dev.p), d_r, sl.qr.p,
-                   PA_F32, static_cast<const float*>(idx->cent_dev.p), r, static_cast<int32_t*>(sl.cl.p), st);
-    (void)r;
-    index_select_entries(idx, static_cast<const float*>(sl.qr.p), static_cast<const int32_t*>(sl.cl.p), m, E,
-                         static_cast<int32_t*>(sl.eid.p), static_cast<float*>(sl.ed.p), static_cast<int32_t*>(sl.scr.p),
-                         st);
-    launch_beam(static_cast<const float*>(sl.qr.p), m, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
-                static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, static_cast<const int32_t*>(sl.eid.p), E, ef,
-                idx->p.metric, 0, static_cast<int32_t*>(sl.bid.p), static_cast<float*>(sl.bd.p),
-                static_cast<int32_t*>(sl.cnt.p), st, static_cast<const int32_t*>(sl.efq.p), PA_VISITED_EXACT,
+    PA_HIP(hipMemcpyAsync(sl.q, qp, sizeof(float) * m * D, hipMemcpyHostToDevice, st));
+    PA_HIP(hipMemcpyAsync(sl.efq, ep, sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+    launch_project(static_cast<const float*>(sl.q), m, D, static_cast<const float*>(idx->V_dev.p), d_r, sl.qr, PA_F32,
+                   static_cast<const float*>(idx->cent_dev.p), r, static_cast<int32_t*>(sl.cl), st);
+    index_select_entries(idx, static_cast<const float*>(sl.qr), static_cast<const int32_t*>(sl.cl), m, E,
+                         static_cast<int32_t*>(sl.eid), static_cast<float*>(sl.ed), static_cast<int32_t*>(sl.scr), st);
+    launch_beam(static_cast<const float*>(sl.qr), m, d_r, idx->Xr_dev.p, idx->p.xr_dtype, idx->xr_rows,
+                static_cast<const int32_t*>(idx->adj_dev.p), idx->R_sub, static_cast<const int32_t*>(sl.eid), E, ef,
+                idx->p.metric, 0, static_cast<int32_t*>(sl.bid), static_cast<float*>(sl.bd),
+                static_cast<int32_t*>(sl.cnt), st, static_cast<const int32_t*>(sl.efq), PA_VISITED_EXACT,
                 index_out_map(idx), false);  // the host stages read only the ids
-    PA_HIP(hipMemcpyAsync(sl.beam_pin.p, sl.bid.p, sizeof(int32_t) * m * ef, hipMemcpyDeviceToHost, st));
+    PA_HIP(hipMemcpyAsync(sl.beam_pin.p, sl.bid, sizeof(int32_t) * m * ef, hipMemcpyDeviceToHost, st));
     PA_HIP(hipEventRecord(sl.done, st));
 }
 
@@ -145,7 +179,7 @@ void scheduler_loop(pa_server* s) {
                     if (s->stop) return true;
                     if (s->pending.empty()) return false;
                     for (auto& x : s->slots)
-                        if (!x->busy) return s->bytes_in_flight + s->pending.front().bytes <= s->p.hbm_budget;
+                        if (!x->busy) return true;
                     return false;
                 });
                 if (s->stop) return;
@@ -158,13 +192,17 @@ void scheduler_loop(pa_server* s) {
                 sl->ef_max = 0;
                 sl->bytes = 0;
                 const double t = now_us(s);
-                while (!s->pending.empty() && static_cast<int>(sl->reqs.size()) < s->p.max_batch &&
-                       s->bytes_in_flight + sl->bytes + s->pending.front().bytes <= s->p.hbm_budget) {
+                // the head of the queue joins while the micro-batch, at its largest list
+                // size, still fits the slot's arena (one request always fits: see create)
+                while (!s->pending.empty() && static_cast<int>(sl->reqs.size()) < s->p.max_batch) {
+                    const int ef = std::max(sl->ef_max, s->pending.front().ef);
+                    const int64_t b = batch_bytes(s->idx, static_cast<int64_t>(sl->reqs.size()) + 1, ef);
+                    if (b > s->arena_bytes) break;
                     Request rq = std::move(s->pending.front());
                     s->pending.pop_front();
                     rq.t_admit = t;
-                    sl->bytes += rq.bytes;
-                    sl->ef_max = std::max(sl->ef_max, rq.ef);
+                    sl->bytes = b;
+                    sl->ef_max = ef;
                     sl->reqs.push_back(std::move(rq));
                 }
                 s->bytes_in_flight += sl->bytes;
@@ -243,21 +281,11 @@ void completion_loop(pa_server* s) {
 
 void alloc_slot(pa_server* s, Slot& sl) {
     pa_index* idx = s->idx;
-    const int64_t B = s->p.max_batch, D = idx->p.dim, d_r = idx->p.d_r, ef = PA_MAX_EF;
-    const int64_t E = entries_for(idx, PA_MAX_EF);
+    const int64_t B = s->p.max_batch, D = idx->p.dim, ef = PA_MAX_EF;
     int64_t& used = idx->hbm_used;
     PA_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
     PA_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    sl.q.ensure(sizeof(float) * B * D, used, 0);
-    sl.qr.ensure(sizeof(float) * B * d_r, used, 0);
-    sl.cl.ensure(sizeof(int32_t) * B, used, 0);
-    sl.eid.ensure(sizeof(int32_t) * B * E, used, 0);
-    sl.ed.ensure(sizeof(float) * B * E, used, 0);
-    sl.bid.ensure(sizeof(int32_t) * B * ef, used, 0);
-    sl.bd.ensure(sizeof(float) * B * ef, used, 0);
-    sl.cnt.ensure(sizeof(int32_t) * B * 4, used, 0);
-    sl.efq.ensure(sizeof(int32_t) * B, used, 0);
-    sl.scr.ensure(sizeof(int32_t) * select_entries_scratch_ints(B, idx->p.r), used, 0);
+    sl.arena.ensure(static_cast<size_t>(s->arena_bytes), used, 0);
     sl.q_pin.ensure(sizeof(float) * B * D);
     sl.beam_pin.ensure(sizeof(int32_t) * B * ef);
     sl.efq_pin.ensure(sizeof(int32_t) * B);
@@ -310,6 +338,16 @@ pa_status pa_server_create(pa_index* idx, const pa_server_params* params, pa_ser
         s->idx = idx;
         s->p = p;
         s->t0 = Clock::now();
+        // the budget holds the index first; the rest is split into the slots' arenas, each
+        // no larger than a full micro-batch at the largest list size
+        const int64_t index_bytes = idx->hbm_used;
+        const int64_t per_slot = (p.hbm_budget - index_bytes) / p.streams / kAlign * kAlign;
+        const int64_t one = batch_bytes(idx, 1, PA_MAX_EF);
+        require(per_slot >= one, "hbm_budget (" + std::to_string(p.hbm_budget) + " bytes) cannot hold the index (" +
+                                     std::to_string(index_bytes) + " bytes) and one request of list size " +
+                                     std::to_string(PA_MAX_EF) + " per slot (" + std::to_string(one) + " bytes)",
+                PA_EHBM);
+        s->arena_bytes = std::min(per_slot, batch_bytes(idx, p.max_batch, PA_MAX_EF));
         for (int i = 0; i < p.streams; ++i) {
             s->slots.push_back(std::make_unique<Slot>());
             alloc_slot(s.get(), *s->slots.back());
@@ -340,8 +378,6 @@ pa_status pa_server_submit(pa_server* s, const float* q_host, int32_t k, int32_t
         rq.ef = std::max(ef, k);
         rq.ef = std::min(rq.ef, static_cast<int>(PA_MAX_EF));
         rq.tag = tag;
-        rq.bytes = request_bytes(s->idx, rq.ef);
-        require(rq.bytes <= s->p.hbm_budget, "a single request exceeds the HBM budget", PA_EHBM);
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (s->error_code != PA_OK) fail(s->error_code, "server failed: " + s->error);
@@ -406,6 +442,10 @@ pa_status pa_server_destroy(pa_server* s) {
             s->cv_done.wait(lk, [&] { return s->completed == s->submitted || s->error_code != PA_OK; });
         }
         shutdown(s);
+        int64_t held = 0;
+        for (auto& sl : s->slots) held += static_cast<int64_t>(sl->arena.bytes);
+        for (auto& sl : s->slots) sl->arena.release();
+        s->idx->hbm_used -= held;
         delete s;
     });
 }

@@ -59,7 +59,9 @@ def exact_knn(X, Q, k: int, metric: str = "l2", *, device=None, exclude_self: bo
             bias = torch.where(cm, torch.zeros(n, device=dev), torch.full((n,), float("inf"), device=dev))
         if budget_bytes is None:
             budget_bytes = (6 << 30) if dev.type == "cuda" else (1 << 29)
-        bs = int(max(1, min(m, budget_bytes // max(1, 4 * n))))
+        # a chunk's score matrix also stays below 2^30 elements (top-k over larger tensors
+        # is not to be relied on)
+        bs = int(max(1, min(m, budget_bytes // max(1, 4 * n), (1 << 30) // max(1, n))))
         out_i = np.empty((m, min(k, n)), dtype=np.int64)
         out_d = np.empty((m, min(k, n)), dtype=np.float64)
         for q0 in range(0, m, bs):

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported(L):
     for name in decl:
         assert hasattr(L, name), name
     assert decl == set(pa.symbols())
-    assert pa.abi_version() == 11
+    assert pa.abi_version() == 12
 
 
 def _csr(rows):

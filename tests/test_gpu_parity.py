@@ -465,15 +465,17 @@ def _big_bucket_tables(tiny, n_p=4096, r=2):
     return P, pivots, b, c.astype(np.float32), EV, EVn, EVid
 
 
-def test_select_entries_chunked_large_bucket(dev, tiny):
-    say("select_entries with 2048-pivot buckets (chunked kernel), E=32")
-    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny)
+@pytest.mark.parametrize("n_p,r,E", [(4096, 2, 32), (4096, 4, 64), (4096, 8, 64), (4096, 32, 128)])
+def test_select_entries_chunked_large_bucket(dev, tiny, n_p, r, E):
+    # buckets of 2,048 pivots (candidate list shrunk chunk by chunk), 1,024 and 512 (scores
+    # in registers) and 128 (one chunk), the last with E equal to the bucket size
+    say(f"select_entries with {n_p // r}-pivot buckets, E={E}")
+    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny, n_p, r)
     Qr = tiny["Qr32"][:300]
-    oi, od, ocl, _ = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 32)
+    oi, od, ocl, margin = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, E)
     ids, d = pa.select_entries(_t(Qr, dev), _t(ocl.astype(np.int32), dev), _t(EV, dev), _t(EVn, dev), _t(EVid, dev),
-                               32)
+                               E)
     ids, d = ids.cpu().numpy(), d.cpu().numpy()
-    _, _, _, margin = oracle.select_entries(Qr, cent.astype(np.float64), b, P, pivots, 32)
     tally = DistTally()
     bad = 0
     for i in range(Qr.shape[0]):
@@ -486,9 +488,11 @@ def test_select_entries_chunked_large_bucket(dev, tiny):
     assert bad <= 1
 
 
-def test_select_entries_fp8_preselect_then_fp32_rerank(dev, tiny):
-    say("select_entries_fp8 with 2048-pivot buckets, E=16, K=64")
-    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny)
+@pytest.mark.parametrize("n_p,r", [(4096, 2), (8192, 2), (4096, 8)])
+def test_select_entries_fp8_preselect_then_fp32_rerank(dev, tiny, n_p, r):
+    # buckets of 2,048 and 512 pivots (scores in registers) and 4,096 (candidate list)
+    say(f"select_entries_fp8 with {n_p // r}-pivot buckets, E=16, K=64")
+    P, pivots, b, cent, EV, EVn, EVid = _big_bucket_tables(tiny, n_p, r)
     codes, scales = pa.quantize_fp8_rows(EV.reshape(-1, EV.shape[-1]))
     EV8 = codes.reshape(EV.shape)
     EVs = scales.reshape(EV.shape[:2])

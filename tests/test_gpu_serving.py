@@ -103,25 +103,47 @@ def test_server_result_is_the_same_alone_in_the_mix_and_in_batch_search(dev, tin
         assert (d[0].view(np.uint32) == mixed[tag]["dists"].view(np.uint32)).all()
 
 
+def _batch_bytes(spec, m, ef):
+    """Device bytes of a micro-batch of m requests at list size ef (the server's documented
+    footprint: each buffer rounded up to 256 bytes)."""
+    al = lambda b: (b + 255) // 256 * 256
+    e = min(ef, spec.n_pivots // spec.r)
+    return (al(4 * m * spec.dim) + al(4 * m * spec.d_r) + al(4 * m) + 2 * al(4 * m * e) + 2 * al(4 * m * ef)
+            + al(16 * m) + al(4 * m) + al(4 * (3 * spec.r + 2 + m)))
+
+
 def test_server_budget_makes_requests_queue(dev, tiny, index):
     s = tiny["spec"]
-    per_req = 4 * s.dim + 4 * s.d_r + 4 + 8 * min(64, s.n_pivots // s.r) + 8 * 64 + 20
-    srv = pa.Server(index, hbm_budget=3 * per_req, max_batch=64, streams=2, threads=2)
-    print("server: budget of three requests, 30 submitted", flush=True)
+    # the index first, then two slots that each hold a micro-batch of three requests at
+    # ef 512 but not four
+    held = index.info()["hbm_bytes"]
+    per_slot = _batch_bytes(s, 3, 512)
+    assert _batch_bytes(s, 4, 512) > per_slot
+    srv = pa.Server(index, hbm_budget=held + 2 * per_slot, max_batch=64, streams=2, threads=2)
+    print("server: budget of the index plus two slots of three requests at ef 512, 30 submitted", flush=True)
     for i in range(30):
-        srv.submit(tiny["Q"][i], 10, 64, i)
+        srv.submit(tiny["Q"][i], 10, 512, i)
     srv.drain()
     res = {r["tag"]: r for r in srv.poll(100)}
     st = srv.stats()
+    srv.close()
+    # the server's arenas are released with it
+    assert index.info()["hbm_bytes"] == held
     assert len(res) == 30 and st["max_batch"] <= 3 and st["batches"] >= 10
-    ids, d, _, _ = index.search(tiny["Q"][:30], 10, 64, 64)
+    ids, d, _, _ = index.search(tiny["Q"][:30], 10, 512, 512)
     for i in range(30):
         assert (res[i]["ids"] == ids[i]).all()
-    srv.close()
+
+
+def test_server_budget_below_the_index_is_refused(dev, tiny, index):
+    held = index.info()["hbm_bytes"]
+    with pytest.raises(pa.PilotannError) as e:
+        pa.Server(index, hbm_budget=held + 1000, streams=2, threads=1)
+    assert e.value.status == -4  # PA_EHBM
 
 
 def test_server_rejects_bad_requests(dev, tiny, index):
-    srv = pa.Server(index, hbm_budget=1 << 20, max_k=100, threads=1)
+    srv = pa.Server(index, hbm_budget=index.info()["hbm_bytes"] + (64 << 20), max_k=100, threads=1)
     q = tiny["Q"][0]
     with pytest.raises(pa.PilotannError) as e:
         srv.submit(q, 0, 64, 1)
@@ -138,11 +160,6 @@ def test_server_rejects_bad_requests(dev, tiny, index):
         srv.submit(bad, 10, 64, 1)
     assert e.value.status == -6
     srv.close()
-    small = pa.Server(index, hbm_budget=100, threads=1)
-    with pytest.raises(pa.PilotannError) as e:
-        small.submit(q, 10, 64, 1)
-    assert e.value.status == -4
-    small.close()
 
 
 def test_server_on_the_compact_layout_matches_the_full_layout(dev, tiny, index):
