@@ -105,9 +105,19 @@ def build_fixture(spec, device, cache=None, nprobe=64):
     from the IVF-restricted builder; ``cache`` (a directory) keeps the graph, the ground
     truth and the subgraph between runs (the vectors are regenerated from their seeds)."""
     from synth import base_vectors, query_vectors, node_order, pivot_choice, kmeans_init_choice
-    from synth.graph import build_graph, build_subgraph_csr, padded_to_csr
+    from synth.graph import build_graph, build_graph_projected, build_subgraph_csr, padded_to_csr
     from synth.ivf import build_graph_ivf, build_subgraph_csr_ivf
     from synth.knn import exact_knn
+    wide = spec.dim >= 512  # graph from the 128 leading principal components
+
+    def graph_of(Xa):
+        if wide:
+            inner = (lambda Y, R: build_graph_ivf(Y, R, nprobe=nprobe, seed=spec.seed, device=device, log=log)) \
+                if large(spec) else None
+            return build_graph_projected(Xa, spec.degree, 128, device=device, builder=inner)
+        if large(spec):
+            return build_graph_ivf(Xa, spec.degree, nprobe=nprobe, seed=spec.seed, device=device, log=log)
+        return build_graph(Xa, spec.degree, device=device)
     t = time.time()
     X = base_vectors(spec)
     Q = query_vectors(spec)
@@ -119,10 +129,7 @@ def build_fixture(spec, device, cache=None, nprobe=64):
         log(f"graph and ground truth from {cache}")
     else:
         t = time.time()
-        if large(spec):
-            adj = build_graph_ivf(X, spec.degree, nprobe=nprobe, seed=spec.seed, device=device, log=log)
-        else:
-            adj = build_graph(X, spec.degree, device=device)
+        adj = graph_of(X)
         log(f"full graph: mean degree {(adj >= 0).sum(1).mean():.2f} in {time.time() - t:.1f}s")
         t = time.time()
         gt, _ = exact_knn(X, Q, spec.k, spec.metric, device=device,
@@ -135,7 +142,14 @@ def build_fixture(spec, device, cache=None, nprobe=64):
             np.save(path("adj"), adj)
             np.save(path("gt"), gt)
     rp, nb = padded_to_csr(adj)
-    if large(spec):
+    if wide:
+        def sub_builder(Xa, mask, R, device=None):
+            sel = np.nonzero(mask)[0]
+            local = graph_of(Xa[sel])
+            full = np.full((Xa.shape[0], R), -1, dtype=np.int32)
+            full[sel] = np.where(local >= 0, sel[np.clip(local, 0, None)], -1)
+            return padded_to_csr(full)
+    elif large(spec):
         def sub_builder(Xa, mask, R, device=None):
             return build_subgraph_csr_ivf(Xa, mask, R, nprobe=nprobe, seed=spec.seed + 3, device=device, log=log)
     else:
@@ -158,15 +172,17 @@ def build_fixture(spec, device, cache=None, nprobe=64):
     return dict(X=X, Q=Q, adj=adj, rp=rp, nb=nb, gt=gt, order=node_order(spec.n, spec.seed),
                 pivot_choice=pivot_choice, kmeans_init_choice=kmeans_init_choice,
                 build_subgraph_csr=builder, device=device,
-                graph="IVF-restricted candidates (%d lists of ~1,024 rows probed)" % nprobe if large(spec)
-                else "exact candidates")
+                graph=("candidates and pruning on the 128 leading principal components, rows ordered by the "
+                       "full distance" if wide else "full vectors")
+                + (f", IVF-restricted candidates ({nprobe} lists of ~1,024 rows probed)" if large(spec)
+                   else ", exact candidates"))
 
 
 def build_index(spec, fx, xr_dtype, shared, compact=False):
     import paper_2503_21206_amd as pa
     t = time.time()
     idx = pa.Index(pa.IndexConfig(dim=spec.dim, d_r=spec.d_r, metric=spec.metric, xr_dtype=xr_dtype, r=spec.r,
-                                  compact=compact))
+                                  compact=compact, pivot_dtype=spec.pivot_dtype))
     idx.set_data(fx["X"], fx["rp"], fx["nb"])
     if "V" not in shared:
         idx.fit_projection()

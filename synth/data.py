@@ -59,6 +59,7 @@ class WorkloadSpec:
     spreads: tuple = ()
     r: int = 32
     xr_dtypes: tuple = ("f32",)
+    pivot_dtype: str = "f32"  # "f32" | "fp8": precision of the entry pivots' scores
     extra: dict = field(default_factory=dict)
 
     @property
@@ -85,8 +86,8 @@ SPECS = {
     "aniso10m": WorkloadSpec(
         name="aniso10m", config=3, n=10_000_000, dim=768, components=1024,
         queries=10_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
-        sample_mode="seed_expand", n_pivots=65_536, ef=(64, 128, 256, 512),
-        kind="aniso", xr_dtypes=("bf16",)),
+        sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256),
+        kind="aniso", xr_dtypes=("bf16",), pivot_dtype="fp8"),
     "gmm100m": WorkloadSpec(
         name="gmm100m", config=4, n=100_000_000, dim=96, components=16_384,
         queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
@@ -101,7 +102,7 @@ SPECS = {
     "serve20m": WorkloadSpec(
         name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
         queries=100_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
-        sample_mode="seed_expand", n_pivots=65_536, ef=(64, 128, 256, 512),
+        sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
         kind="aniso", xr_dtypes=("f16",)),
 }
 

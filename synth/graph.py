@@ -245,6 +245,36 @@ def _sort_rows(X: np.ndarray, adj: np.ndarray, device=None) -> np.ndarray:
     return out.cpu().numpy()
 
 
+@torch.no_grad()
+def leading_components(X: np.ndarray, dims: int, device=None) -> np.ndarray:
+    """The ``dims`` leading eigenvectors of X's centred second moment (fp64), [D][dims]."""
+    dev = pick_device(device)
+    x = torch.as_tensor(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    G = torch.zeros((x.shape[1], x.shape[1]), dtype=torch.float64, device=dev)
+    mu = torch.zeros(x.shape[1], dtype=torch.float64, device=dev)
+    for a in range(0, x.shape[0], 1 << 20):
+        xa = x[a:a + (1 << 20)].double()
+        G += xa.T @ xa
+        mu += xa.sum(0)
+    n = x.shape[0]
+    C = (G / n - torch.outer(mu / n, mu / n)).cpu().numpy()
+    w, V = np.linalg.eigh(C)
+    return V[:, ::-1][:, :dims].copy()
+
+
+def build_graph_projected(X: np.ndarray, R: int, dims: int, *, device=None, builder=None) -> np.ndarray:
+    """Graph for high-dimensional rows: candidates, pruning and repair on the ``dims``
+    leading principal components (``builder``, the exact builder by default), then every
+    row ordered by the full distance.  Distances in the projected space under-estimate the
+    full ones by the residual energy only, so the near candidates are largely the same
+    rows; the full-space scoring of those candidates would cost D / dims times more."""
+    V = leading_components(X, dims, device)
+    Xp = (X.astype(np.float64) @ V).astype(np.float32)
+    build = builder or (lambda Y, R_: build_graph(Y, R_, device=device))
+    adj = build(Xp, R)
+    return _sort_rows(X, adj.astype(np.int64), device).astype(np.int32)
+
+
 def padded_to_csr(adj: np.ndarray):
     """[n][R] padded rows -> (rowptr int64 [n+1], nbrs int32)."""
     deg = (adj >= 0).sum(1)
