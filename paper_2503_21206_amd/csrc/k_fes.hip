@@ -45,64 +45,60 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // scratch (int32): [0, r) counts | [r, 2r+1) offsets | [2r+1, 3r+2) tile prefix | perm[m]
-// One block; every wavefront aggregates its 64 queries per cluster with ballots, so the
-// shared counters see one atomic per (wavefront, cluster) present instead of one per query.
-__global__ __launch_bounds__(1024) void group_kernel(const int32_t* __restrict__ cluster, int64_t m, int r,
-                                                     int32_t* __restrict__ scratch) {
-    __shared__ int cnt[kMaxClusters];
-    __shared__ int cur[kMaxClusters];
-    __shared__ int off[kMaxClusters + 1];
-    const int t = threadIdx.x, lane = t & 63;
-    if (t < kMaxClusters) {
-        cnt[t] = 0;
-        cur[t] = 0;
-    }
+// One block of 16 wavefronts.  Each wavefront counts its queries in a private histogram
+// (no contention between wavefronts); the counts give every (wavefront, cluster) pair its
+// own run of the permutation, which the second pass fills.
+constexpr int kGroupWaves = 16;
+__global__ __launch_bounds__(64 * kGroupWaves) void group_kernel(const int32_t* __restrict__ cluster, int64_t m,
+                                                                   int r, int32_t* __restrict__ scratch) {
+    __shared__ int hist[kGroupWaves][kMaxClusters];
+    __shared__ int base[kGroupWaves][kMaxClusters];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int i = t; i < kGroupWaves * kMaxClusters; i += 64 * kGroupWaves) (&hist[0][0])[i] = 0;
     __syncthreads();
-    for (int64_t i0 = t - lane; i0 < m; i0 += 1024) {
+    // wavefront w takes queries [w, w + 16, ...) in runs of 64
+    for (int64_t i0 = static_cast<int64_t>(w) * 64; i0 < m; i0 += 64 * kGroupWaves) {
         const int64_t i = i0 + lane;
-        int c = i < m ? cluster[i] : -1;
-        if (c < 0 || c >= r) c = -1;
-        uint64_t todo = __ballot(c >= 0);
-        while (todo) {
-            const int lead = __builtin_ctzll(todo);
-            const int cc = __builtin_amdgcn_readlane(c, lead);
-            const uint64_t same = __ballot(c == cc);
-            if (lane == lead) atomicAdd(&cnt[cc], __popcll(same));
-            todo &= ~same;
-        }
+        const int c = i < m ? cluster[i] : -1;
+        if (c >= 0 && c < r) atomicAdd(&hist[w][c], 1);
     }
     __syncthreads();
-    if (t == 0) {
-        int o = 0, tp = 0;
-        for (int c = 0; c < r; ++c) {
-            off[c] = o;
-            scratch[c] = cnt[c];
-            scratch[r + c] = o;
-            scratch[2 * r + 1 + c] = tp;
-            o += cnt[c];
-            tp += (cnt[c] + kTQ - 1) / kTQ;
+    if (w == 0) {  // lane c: cluster c's count, then exclusive prefix sums over the clusters
+        int cnt = 0;
+        if (lane < r)
+            for (int v = 0; v < kGroupWaves; ++v) cnt += hist[v][lane];
+        const int tiles = (cnt + kTQ - 1) / kTQ;
+        int o = cnt, tp = tiles;  // inclusive scans
+        for (int d = 1; d < 64; d <<= 1) {
+            const int a = __shfl_up(o, d), b = __shfl_up(tp, d);
+            if (lane >= d) {
+                o += a;
+                tp += b;
+            }
         }
-        off[r] = o;
-        scratch[2 * r] = o;
-        scratch[3 * r + 1] = tp;
+        o -= cnt;
+        tp -= tiles;
+        if (lane < r) {
+            scratch[lane] = cnt;
+            scratch[r + lane] = o;
+            scratch[2 * r + 1 + lane] = tp;
+            int run = o;
+            for (int v = 0; v < kGroupWaves; ++v) {
+                base[v][lane] = run;
+                run += hist[v][lane];
+            }
+        }
+        if (lane == r - 1) {
+            scratch[2 * r] = o + cnt;
+            scratch[3 * r + 1] = tp + tiles;
+        }
     }
     __syncthreads();
     int32_t* perm = scratch + 3 * r + 2;
-    for (int64_t i0 = t - lane; i0 < m; i0 += 1024) {
+    for (int64_t i0 = static_cast<int64_t>(w) * 64; i0 < m; i0 += 64 * kGroupWaves) {
         const int64_t i = i0 + lane;
-        int c = i < m ? cluster[i] : -1;
-        if (c < 0 || c >= r) c = -1;
-        uint64_t todo = __ballot(c >= 0);
-        while (todo) {
-            const int lead = __builtin_ctzll(todo);
-            const int cc = __builtin_amdgcn_readlane(c, lead);
-            const uint64_t same = __ballot(c == cc);
-            int base = 0;
-            if (lane == lead) base = atomicAdd(&cur[cc], __popcll(same));
-            base = __builtin_amdgcn_readlane(base, lead);
-            if (c == cc) perm[off[cc] + base + mbcnt(same)] = static_cast<int32_t>(i);
-            todo &= ~same;
-        }
+        const int c = i < m ? cluster[i] : -1;
+        if (c >= 0 && c < r) perm[atomicAdd(&base[w][c], 1)] = static_cast<int32_t>(i);
     }
 }
 
@@ -686,7 +682,7 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
                        (fp8 ? static_cast<size_t>(kTQ) * d : 0);
     require(cap <= 16 * 64 && lds <= static_cast<size_t>(max_lds),
             "FES candidate list of a 16-query tile does not fit in LDS", PA_EUNSUPPORTED);
-    hipLaunchKernelGGL(group_kernel, dim3(1), dim3(1024), 0, s, cluster, m, r, scratch_i32);
+    hipLaunchKernelGGL(group_kernel, dim3(1), dim3(64 * kGroupWaves), 0, s, cluster, m, r, scratch_i32);
     PA_HIP(hipGetLastError());
     FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, cap, metric, scratch_i32, ids, dists};
     const int blocks = static_cast<int>((m + kTQ - 1) / kTQ) + r;

@@ -97,7 +97,7 @@ SPECS = {
     "aniso100m": WorkloadSpec(
         name="aniso100m", config=4, n=100_000_000, dim=96, components=16_384,
         queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
-        sample_mode="seed_expand", n_pivots=16_384, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
+        sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
         kind="aniso", unit_norm=False, xr_dtypes=("f16",)),
     "serve20m": WorkloadSpec(
         name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
