@@ -837,6 +837,8 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=32 << 30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy kernel (counter calibration for profiles)")
+    ap.add_argument("--calibration-only", action="store_true",
+                    help="run only the 1 GiB copy kernel of --copy-calibration and exit")
     ap.add_argument("--no-flat", dest="flat", action="store_false",
                     help="skip the flat-mixture leg (the same shape, centres ~ N(0, 4I))")
     ap.add_argument("--ef", default="",
@@ -860,6 +862,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibration_only:
+        copy_calibration()
+        return
     import paper_2503_21206_amd as pa
     from synth import SPECS
     pa.device_init(0)
@@ -931,6 +936,8 @@ def main():
                                   "cache slot) instead of the exact cache", True, 1),
                         "width2": ("two unchecked entries expanded per step (not the paper's Algorithm 1)", False, 2),
                         "bloom+width2": ("both", True, 2)}
+            if spec.degree > 32:  # expansion width 2 takes subgraph degrees up to 32
+                variants = {"bloom": variants["bloom"]}
             forms[form]["variants"] = {}
             for name, (what, bloom, width) in variants.items():
                 dtb, aggb, recb = timed(idx, spec, fx, ef, args.steps, args.warmup, bloom=bloom, width=width)
@@ -1015,12 +1022,19 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, fx, shared, (f["ef_gpu"], f["ef_cpu"]), args.cpu_budget, plain_ef)
     print(json.dumps(out), flush=True)
     if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 2.0, out=dst)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
+        copy_calibration()
+
+
+def copy_calibration():
+    """One elementwise kernel that reads 1 GiB and writes 1 GiB: what a counter reads for
+    it scales the same counter on the other kernels to bytes."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    log("copy calibration: 1073741824 bytes read, 1073741824 bytes written")
 
 
 if __name__ == "__main__":

@@ -109,9 +109,9 @@ pa_status pa_fit_projection(const float* X_host, int64_t N, int32_t D, int32_t d
                             double* mean_host);
 
 /* Y_dev [n][d_r] = X_dev [n][D] * V_dev [D][d_r]: the reduced vectors x_primary of section
- * 4.1.  Each fp32 output is the exact product rounded once to fp32 (compensated fp32
- * accumulation; it can differ by one ulp only where the exact value lies within about
- * 2^-44 of sum |x_k v_k| of a rounding midpoint), independent of n and of the other rows;
+ * 4.1.  Each fp32 output is the exact product rounded once to fp32 (the exact fp32
+ * products accumulated in fp64; it can differ by one ulp only where the exact value lies
+ * within D 2^-53 of sum |x_k v_k| of a rounding midpoint), independent of n and of the other rows;
  * PA_F16 / PA_BF16 outputs are that fp32 value rounded to nearest even.
  * d_r % 16 == 0, d_r <= PA_MAX_DR, D <= 4096. */
 pa_status pa_project(const float* X_dev, int64_t n, int32_t D, const float* V_dev,

@@ -105,8 +105,9 @@ __global__ __launch_bounds__(64 * kGroupWaves) void group_kernel(const int32_t* 
 // ---------------------------------------------------------------- pivot scoring
 // One block per (cluster, 16-query tile); one wavefront per query row of the tile.
 //
-// The bucket is scanned in chunks of kCH pivots.  Per chunk the block scores the 16 x kCH
-// tile on MFMA in the expanded form ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP): FP32
+// The bucket is scanned in chunks of CH pivots (128, or 256 with the scores in registers).
+// Per chunk the block scores the 16 x CH tile on MFMA in the expanded form
+// ||q||^2 + ||p||^2 - 2 q.p (L2) or -q.p (IP): FP32
 // form v_mfma_f32_16x16x4f32; FP8 form v_mfma_f32_16x16x32_fp8_fp8 on per-row e4m3 codes
 // (queries encoded on the fly like the pivots: scale = max|q| / 448, round to nearest
 // even).  Each row's wavefront then offers the chunk's pivots to the row's candidate
@@ -118,16 +119,25 @@ __global__ __launch_bounds__(64 * kGroupWaves) void group_kernel(const int32_t* 
 //   4 (d + 4) of them).  T is the E-th smallest upper end score + eps among the pivots
 //   seen so far; a pivot whose lower end score - eps exceeds T has at least E pivots
 //   certainly closer and can never be in the top E.  Every other pivot stays.  At the end
-//   the survivors (typically E and a few near the boundary) are re-scored exactly: direct
-//   form in float-float, the correctly rounded fp32 distance, independent of summation
-//   order; the top E by (distance, node id) are emitted in order.  The result is the exact
-//   top E, whatever the rounding of the MFMA pass.
+//   the survivors (typically E and a few near the boundary) are re-scored exactly (the
+//   direct form in fp64, rounded once to fp32: below) and the top E by (distance, node id)
+//   are emitted in order.  The result is the exact top E, whatever the rounding of the
+//   MFMA pass.
 // * FP8 form (approximate, the paper's reduced-precision selection).  The buffer keeps the
 //   K best pivots by (FP8 score, position); these are re-scored exactly and the top E by
 //   (distance, node id) are emitted.
 //
 // The E-th / K-th smallest value of a buffer is found by a bitwise search over the ordered
 // encoding (one ballot per buffer slot and bit), so no sort runs before the final E.
+//
+// Exact distances.  Each term of the direct form is formed in fp64 (the difference of two
+// fp32 values, or the product of two fp32 values, which is exact) and accumulated by fp64
+// fmas; four lanes share a pivot and their partial sums are added pairwise, the same way on
+// every lane.  The fp64 sum is within (d + 4) 2^-53 of sum |term| of the exact value and is
+// rounded once to fp32: the correctly rounded distance unless the exact one lies within
+// that distance of a rounding boundary of fp32 (2^29 times closer than fp32's own spacing).
+// One fp64 fma per term replaces a float-float update of about 15 fp32 instructions, at
+// the same issue rate on CDNA.
 typedef long fp8x8 __attribute__((ext_vector_type(1)));
 
 __device__ __forceinline__ uint8_t dev_f32_to_e4m3(float x) {
@@ -162,6 +172,7 @@ struct FesArgs {
     const float* EVnorm;
     const int32_t* EVid;
     int r, n_b, E, K, cap, metric;  // K: FP8 pre-selection size; cap: buffer entries per row
+    int xcd;                        // 1: tiles grouped by XCD (pivot tables larger than an L2)
     const int32_t* scratch;
     int32_t* out_ids;
     float* out_d;
@@ -172,6 +183,14 @@ __device__ __forceinline__ float dpp(float v) {
     return __builtin_bit_cast(float,
                               __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(u & 0xFFFFFFFFu), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                          static_cast<uint32_t>(lo));
+}
 __device__ __forceinline__ float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -181,20 +200,105 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// Smallest v with #{valid x_i <= v} >= k (k >= 1, at least k valid entries), over S values
-// per lane; bitwise from the top, one ballot per slot and bit.
+// A threshold v with exactly the k smallest valid values <= v when the k-th and (k+1)-th
+// differ, else the smallest v with #{valid x_i <= v} >= k (k >= 1, at least k valid
+// entries), over S values per lane.  Bitwise from the highest bit in which the valid
+// values differ (the bits above it are common to all of them), one ballot per slot and
+// bit; it stops at the first probe that has exactly k values at or below it.  Either
+// result selects the same set {x <= v}.
+template <typename T>
+__device__ __forceinline__ T wave_min_t(T v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const T w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max_t(T v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const T w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
 template <typename T, int BITS, int S>
 __device__ T kth_smallest(const T (&x)[S], const bool (&ok)[S], int slots, int k) {
-    T v = 0;
-    for (int bit = BITS - 1; bit >= 0; --bit) {
+    T lo = ~T(0), hi = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < slots && ok[i]) {
+            lo = x[i] < lo ? x[i] : lo;
+            hi = x[i] > hi ? x[i] : hi;
+        }
+    }
+    lo = wave_min_t(lo);
+    hi = wave_max_t(hi);
+    if (lo == hi) return lo;
+    const int top = (BITS == 64) ? 63 - __clzll(static_cast<unsigned long long>(lo ^ hi))
+                                 : 31 - __clz(static_cast<unsigned int>(lo ^ hi));
+    T v = lo & ~((T(2) << top) - 1);  // the common prefix (top < BITS - 1 here, or T(2) << top wraps to 0)
+    if (top == BITS - 1) v = 0;
+    for (int bit = top; bit >= 0; --bit) {
         const T probe = v | ((T(1) << bit) - 1);
         int c = 0;
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (i < slots) c += __popcll(__ballot(ok[i] && x[i] <= probe));
+        if (c == k) return probe;
         if (c < k) v |= T(1) << bit;
     }
     return v;
+}
+
+// Narrows the search for the k-th smallest valid x (1 <= k < valid) while more values than
+// `room` share its leading bits.  Returns b >= 0 when the values in [v, v | (2^b - 1)]
+// (those sharing v's bits above b) number at most `room`, with `below` values under v; or
+// -1 with v a threshold: exactly k values are <= v (`exact`), or v is the k-th smallest
+// value itself and some of the values equal to it are taken.  Bitwise from the highest
+// bit in which the values differ, one ballot per slot and bit.
+template <int S>
+__device__ int narrow_kth(const uint32_t (&x)[S], const bool (&ok)[S], int slots, int k, int valid, int room,
+                          uint32_t& v, int& below, bool& exact) {
+    uint32_t lo = ~0u, hi = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < slots && ok[i]) {
+            lo = x[i] < lo ? x[i] : lo;
+            hi = x[i] > hi ? x[i] : hi;
+        }
+    }
+    lo = wave_min_t(lo);
+    hi = wave_max_t(hi);
+    below = 0;
+    exact = false;
+    if (lo == hi) {
+        v = lo;
+        return -1;
+    }
+    const int top = 31 - __clz(lo ^ hi);
+    v = top == 31 ? 0u : (lo & ~((2u << top) - 1));
+    int upper = valid;  // values <= v | (2^(bit+1) - 1)
+    for (int bit = top; bit >= 0; --bit) {
+        const uint32_t probe = v | ((1u << bit) - 1);
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < slots) c += __popcll(__ballot(ok[i] && x[i] <= probe));
+        if (c == k) {
+            v = probe;
+            exact = true;
+            return -1;
+        }
+        if (c < k) {
+            below = c;
+            v |= 1u << bit;
+        } else {
+            upper = c;
+        }
+        if (upper - below <= room) return bit;
+    }
+    return -1;
 }
 
 // The state of one row: its candidate buffer in LDS and the running threshold.  An entry
@@ -293,41 +397,51 @@ struct Row {
         store_kept(kk, ee, keep, slots);
     }
 
-    // Re-scores every entry exactly: four lanes per pivot, each over a quarter of the
-    // dimensions in float-float (pieces of up to 32 elements, all loads of a piece issued
-    // before its arithmetic), combined symmetrically across the quad, so the value is the
-    // correctly rounded distance whatever the summation order.  Sixteen pivots per pass.
-    __device__ void rescore(const float* qv, bool node_ids = false, int from = 0) {
-        const int d = a.d, per = d / 4, sub = lane & 3;
+    // Re-scores every entry exactly (fp64 direct form, rounded once): four lanes per pivot,
+    // lane s of the four taking the row's 16-byte pieces s, s + 4, s + 8, ... (a quad reads
+    // 64 contiguous bytes of the pivot per step, and the query's matching fp64 elements,
+    // 128 contiguous bytes of LDS, without bank conflicts); up to 4 pieces per lane and the
+    // node id are loaded before the arithmetic.  Sixteen pivots per pass.  qv: the query
+    // row in fp64.
+    __device__ void rescore(const double* qv, bool node_ids = false, int from = 0) {
+        const int d = a.d, nq = d / 16, sub = lane & 3;  // pieces per lane (d % 16 == 0)
+        constexpr int PW = 4;  // pieces loaded together
         for (int base = from; base < cnt; base += 16) {
             const int t = base + (lane >> 2);
             const bool live = t < cnt;
             const int pos = live ? static_cast<int>(key[t] & 0xFFFFFFFFu) : 0;
-            const float4* pv = reinterpret_cast<const float4*>(a.EV + (cb + pos) * d + sub * per);
-            const float* q4 = qv + sub * per;
-            ff32 acc{0.0f, 0.0f};
-            for (int seg = 0; seg < per; seg += 32) {
-                const int n4 = min(32, per - seg) / 4;
-                float4 x[8];
+            const float4* pv = reinterpret_cast<const float4*>(a.EV + (cb + pos) * d);
+            const uint32_t low = (node_ids && live && sub == 0) ? static_cast<uint32_t>(a.EVid[cb + pos])
+                                                               : static_cast<uint32_t>(pos);
+            double acc = 0.0;
+            for (int s0 = 0; s0 < nq; s0 += PW) {
+                float4 x[PW];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) x[u] = (u < n4 && live) ? pv[seg / 4 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int u = 0; u < PW; ++u)
+                    x[u] = (s0 + u < nq && live) ? pv[4 * (s0 + u) + sub] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    if (u < n4) {
+                for (int u = 0; u < PW; ++u) {
+                    if (s0 + u < nq) {
+                        const double2* q2 = reinterpret_cast<const double2*>(qv + 4 * (4 * (s0 + u) + sub));
+                        const double2 qa = q2[0], qb = q2[1];
+                        const double qd[4] = {qa.x, qa.y, qb.x, qb.y};
                         const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
-                            if (a.metric == PA_METRIC_L2) ff_add_sqdiff(acc, q4[seg + 4 * u + c], xv[c]);
-                            else ff_add_prod(acc, q4[seg + 4 * u + c], xv[c]);
+                            if (a.metric == PA_METRIC_L2) {
+                                const double df = qd[c] - static_cast<double>(xv[c]);
+                                acc = __builtin_fma(df, df, acc);
+                            } else {
+                                acc = __builtin_fma(qd[c], static_cast<double>(xv[c]), acc);
+                            }
                         }
                     }
                 }
             }
-            acc = ff_add(acc, ff32{dpp<0xB1>(acc.hi), dpp<0xB1>(acc.lo)});  // lane ^ 1
-            acc = ff_add(acc, ff32{dpp<0x4E>(acc.hi), dpp<0x4E>(acc.lo)});  // lane ^ 2
-            const float v = (a.metric == PA_METRIC_L2) ? acc.hi : -acc.hi;
+            acc += dpp64<0xB1>(acc);  // lane ^ 1
+            acc += dpp64<0x4E>(acc);  // lane ^ 2
+            const float v = (a.metric == PA_METRIC_L2) ? static_cast<float>(acc) : -static_cast<float>(acc);
             if (live && sub == 0) {
-                const uint32_t low = node_ids ? static_cast<uint32_t>(a.EVid[cb + pos]) : static_cast<uint32_t>(pos);
                 key[t] = (static_cast<uint64_t>(ord_f32(v)) << 32) | low;
                 if (!FP8) eps[t] = 0.0f;
             }
@@ -365,10 +479,14 @@ struct Row {
 template <bool FP8, int S, int SL>
 __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    // pivots per chunk: the register path takes 256 (one 16 x 16 block per wavefront, half
+    // as many block barriers), the list path 128 (its list keeps room for one chunk)
+    constexpr int CH = SL > 0 ? 2 * kCH : kCH;
     const int d = a.d;
-    float* Aq = reinterpret_cast<float*>(smem);                      // [kTQ][d]
-    float* sc = Aq + kTQ * d;                                        // [kTQ][kCH] chunk scores
-    uint64_t* bkey = reinterpret_cast<uint64_t*>(sc + kTQ * kCH);    // [kTQ][cap]
+    double* Aq64 = reinterpret_cast<double*>(smem);                  // [kTQ][d] the rows in fp64
+    float* Aq = reinterpret_cast<float*>(Aq64 + kTQ * d);            // [kTQ][d]
+    float* sc = Aq + kTQ * d;                                        // [kTQ][CH] chunk scores
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(sc + kTQ * CH);    // [kTQ][cap]
     float* beps = reinterpret_cast<float*>(bkey + kTQ * a.cap);      // [kTQ][cap] (FP32 form)
     uint8_t* Aq8 = reinterpret_cast<uint8_t*>(beps + (FP8 ? 0 : kTQ * a.cap));  // [kTQ][d] (FP8)
     __shared__ int qidx[kTQ];
@@ -381,7 +499,12 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     const int32_t* offsets = a.scratch + r;
     const int32_t* tprefix = a.scratch + 2 * r + 1;
     const int32_t* perm = a.scratch + 3 * r + 2;
-    const int b = blockIdx.x;
+    // workgroups go to the 8 XCDs round robin (workgroup i to XCD i mod 8).  With xcd set,
+    // tile b of the cluster-ordered tiles is given to workgroup 8 (b mod T) + b / T
+    // (T = gridDim.x / 8): every XCD takes a contiguous run of tiles (a few whole clusters),
+    // so the pivots it reads stay in its L2
+    const int b = a.xcd ? static_cast<int>(blockIdx.x % 8) * static_cast<int>(gridDim.x / 8) + static_cast<int>(blockIdx.x / 8)
+                        : static_cast<int>(blockIdx.x);
     if (w == 0) {
         // this block's cluster: the number of clusters whose tiles all come before tile b
         // (the tile prefix is non-decreasing)
@@ -406,9 +529,14 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     const int d4 = d / 4;
     for (int idx = t; idx < kTQ * d4; idx += kThreads) {
         const int i = idx / d4, j = idx - i * d4;
-        reinterpret_cast<float4*>(Aq)[idx] =
-            (i < cntq) ? reinterpret_cast<const float4*>(a.Qr + static_cast<int64_t>(qidx[i]) * d)[j]
-                       : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 v = (i < cntq) ? reinterpret_cast<const float4*>(a.Qr + static_cast<int64_t>(qidx[i]) * d)[j]
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+        reinterpret_cast<float4*>(Aq)[idx] = v;
+        double* q64 = Aq64 + 4 * idx;
+        q64[0] = v.x;
+        q64[1] = v.y;
+        q64[2] = v.z;
+        q64[3] = v.w;
     }
     __syncthreads();
     {  // the row's squared norm and FP8 scale (one wavefront per row)
@@ -439,19 +567,31 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     const int g = lane >> 4, col = lane & 15;
     float sv[SL > 0 ? SL : 1], se[SL > 0 ? SL : 1];  // register path: the row's scores and bounds
 #pragma unroll
-    for (int ci = 0; ci < (SL > 0 ? SL / 2 : 1 << 30); ++ci) {
-        const int c0 = ci * kCH;
+    for (int ci = 0; ci < (SL > 0 ? SL / (CH / 64) : 1 << 30); ++ci) {
+        const int c0 = ci * CH;
         if (c0 >= n_b) break;
-        if (w < kCH / 16) {  // one 16 x 16 block of the tile per wavefront
+        if (w < CH / 16) {  // one 16 x 16 block of the tile per wavefront
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int p = c0 + w * 16 + col;
             const bool pv = p < n_b;
             if (FP8) {
-                for (int k = 0; k < d; k += 32) {
-                    long av, bv = 0;
-                    __builtin_memcpy(&av, Aq8 + col * d + k + 8 * g, 8);
-                    if (pv) __builtin_memcpy(&bv, a.EV8 + (cb + p) * d + k + 8 * g, 8);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+                for (int k0 = 0; k0 < d; k0 += 256) {  // the pivot's loads of 8 k-steps in flight together
+                    long bv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        bv[u] = 0;
+                        const int k = k0 + 32 * u;
+                        if (pv && k < d) __builtin_memcpy(&bv[u], a.EV8 + (cb + p) * d + k + 8 * g, 8);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int k = k0 + 32 * u;
+                        if (k < d) {
+                            long av;
+                            __builtin_memcpy(&av, Aq8 + col * d + k + 8 * g, 8);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv[u], acc, 0, 0, 0);
+                        }
+                    }
                 }
             } else {
                 // product step s = 4 i + e takes element 16 i + 4 g + e in lane group g, so
@@ -459,13 +599,13 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                 const float4* prow = reinterpret_cast<const float4*>(a.EV + (cb + (pv ? p : 0)) * d);
                 const float4* qrow = reinterpret_cast<const float4*>(Aq + col * d);
                 const int n16 = d / 16;
-                for (int i0 = 0; i0 < n16; i0 += 8) {
-                    float4 bv[8];
+                for (int i0 = 0; i0 < n16; i0 += 4) {
+                    float4 bv[4];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
+                    for (int u = 0; u < 4; ++u)
                         bv[u] = (pv && i0 + u < n16) ? prow[4 * (i0 + u) + g] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                    for (int u = 0; u < 4; ++u) {
                         if (i0 + u < n16) {
                             const float4 av = qrow[4 * (i0 + u) + g];
                             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[u].x, acc, 0, 0, 0);
@@ -482,7 +622,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
             for (int i = 0; i < 4; ++i) {  // output element i of the lane: row 4 g + i, column col
                 const int rw = 4 * g + i;
                 const float dot = FP8 ? acc[i] * (qs[rw] * ps) : acc[i];
-                sc[rw * kCH + w * 16 + col] =
+                sc[rw * CH + w * 16 + col] =
                     (a.metric == PA_METRIC_L2) ? __builtin_fmaf(-2.0f, dot, qn[rw] + pn) : -dot;
             }
         }
@@ -490,34 +630,34 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
         if constexpr (SL > 0) {
             if (w < cntq) {
 #pragma unroll
-                for (int h = 0; h < kCH / 64; ++h) {
+                for (int h = 0; h < CH / 64; ++h) {
                     const int p = c0 + 64 * h + lane;
-                    sv[2 * ci + h] = sc[w * kCH + 64 * h + lane];
-                    se[2 * ci + h] = (!FP8 && p < n_b) ? a.EVnorm[cb + p] : 0.0f;  // the norm, for now
+                    sv[(CH / 64) * ci + h] = sc[w * CH + 64 * h + lane];
+                    se[(CH / 64) * ci + h] = (!FP8 && p < n_b) ? a.EVnorm[cb + p] : 0.0f;  // the norm, for now
                 }
             }
         } else if (w < cntq) {
             const float qnw = qn[w];
-            float pn[kCH / 64];
+            float pn[CH / 64];
 #pragma unroll
-            for (int h = 0; h < kCH / 64; ++h) {  // all norm loads in flight before the offers
+            for (int h = 0; h < CH / 64; ++h) {  // all norm loads in flight before the offers
                 const int p = c0 + 64 * h + lane;
                 pn[h] = (!FP8 && p < n_b) ? a.EVnorm[cb + p] : 0.0f;
             }
 #pragma unroll
-            for (int h = 0; h < kCH / 64; ++h) {
+            for (int h = 0; h < CH / 64; ++h) {
                 const int p = c0 + 64 * h + lane;
                 const bool ok = p < n_b;
-                const float v = sc[w * kCH + 64 * h + lane];
+                const float v = sc[w * CH + 64 * h + lane];
                 const float e = (!FP8 && ok) ? eps_c * (qnw + pn[h] + fabsf(v)) : 0.0f;
                 row.offer(ok, v, e, p);
             }
-            if (row.cnt > a.cap - kCH) {
+            if (row.cnt > a.cap - CH) {
                 row.shrink(want);
-                if (!FP8 && row.cnt > a.cap - kCH) {
+                if (!FP8 && row.cnt > a.cap - CH) {
                     // (the FP8 list keeps exactly K) more near ties around the
                     // threshold than the slack holds; decide them on exact distances now
-                    row.rescore(Aq + w * d);
+                    row.rescore(Aq64 + w * d);
                     const uint32_t worst = row.keep_best(a.E);
                     row.T32 = worst < row.T32 ? worst : row.T32;
                 }
@@ -543,26 +683,57 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
             const int k = min(a.K, valid);
 #pragma unroll
             for (int i = 0; i < SL; ++i) key[i] = ok[i] ? ord_f32(sv[i]) : 0xFFFFFFFFu;
-            const uint32_t T = kth_smallest<uint32_t, 32, SL>(key, ok, used, k);
+            uint32_t T = 0xFFFFFFFFu;
             int below = 0;
+            bool exact = false;
+            // the search is narrowed over all of the row's scores until the candidates for
+            // the K-th fit the row's list; they are finished there by (score, position)
+            const int nbit = k == valid ? -1 : narrow_kth<SL>(key, ok, used, k, valid, a.cap, T, below, exact);
+            if (nbit >= 0) {
+                const uint32_t top_r = T | ((1u << nbit) - 1);
 #pragma unroll
-            for (int i = 0; i < SL; ++i)
-                if (i < used) below += __popcll(__ballot(ok[i] && key[i] < T));
-            int ties = 0;
+                for (int i = 0; i < SL; ++i) {
+                    if (i < used) {
+                        const bool in = ok[i] && key[i] >= T && key[i] <= top_r;
+                        const uint64_t m = __ballot(in);
+                        if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(key[i]) << 32) | (64 * i + lane);
+                        row.cnt += __popcll(m);
+                    }
+                }
+                wave_sync();
+                row.shrink(k - below);
 #pragma unroll
-            for (int i = 0; i < SL; ++i) {
-                if (i < used) {
-                    const bool tie = ok[i] && key[i] == T;
-                    const uint64_t tm = __ballot(tie);
-                    const bool in = ok[i] && (key[i] < T || (tie && ties + mbcnt(tm) < k - below));
-                    ties += __popcll(tm);
-                    const uint64_t m = __ballot(in);
-                    if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(key[i]) << 32) | (64 * i + lane);
-                    row.cnt += __popcll(m);
+                for (int i = 0; i < SL; ++i) {  // and every score under the range
+                    if (i < used) {
+                        const bool in = ok[i] && key[i] < T;
+                        const uint64_t m = __ballot(in);
+                        if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(key[i]) << 32) | (64 * i + lane);
+                        row.cnt += __popcll(m);
+                    }
+                }
+            } else {
+                if (k < valid) {
+                    below = 0;
+#pragma unroll
+                    for (int i = 0; i < SL; ++i)
+                        if (i < used) below += __popcll(__ballot(ok[i] && key[i] < T));
+                }
+                int ties = 0;
+#pragma unroll
+                for (int i = 0; i < SL; ++i) {
+                    if (i < used) {
+                        const bool tie = ok[i] && key[i] == T;
+                        const uint64_t tm = __ballot(tie);
+                        const bool in = ok[i] && (key[i] < T || (tie && ties + mbcnt(tm) < k - below));
+                        ties += __popcll(tm);
+                        const uint64_t m = __ballot(in);
+                        if (in) row.key[row.cnt + mbcnt(m)] = (static_cast<uint64_t>(key[i]) << 32) | (64 * i + lane);
+                        row.cnt += __popcll(m);
+                    }
                 }
             }
             wave_sync();
-            row.rescore(Aq + w * d, true);
+            row.rescore(Aq64 + w * d, true);
         } else {
             // drop the scores whose lower end exceeds the E-th smallest upper end
             const float qnw = qn[w];
@@ -579,7 +750,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                     const bool in = ok[i] && (!Row<FP8, S>::finite(sv[i]) || Row<FP8, S>::lo_ord(sv[i], se[i]) <= T);
                     const uint64_t m = __ballot(in);
                     if (row.cnt + __popcll(m) > a.cap) {  // near ties beyond the slack: decide a batch
-                        row.rescore(Aq + w * d, true, exact);
+                        row.rescore(Aq64 + w * d, true, exact);
                         row.keep_best(a.E, true);
                         exact = row.cnt;
                     }
@@ -588,17 +759,20 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                 }
             }
             wave_sync();
-            row.rescore(Aq + w * d, true, exact);
+            row.rescore(Aq64 + w * d, true, exact);
         }
     } else {
         row.shrink(want);
-        row.rescore(Aq + w * d, true);
+        row.rescore(Aq64 + w * d, true);
     }
-    row.keep_best(a.E, true);
-    // emit in (distance, node id) order: the rank of each kept key among the kept keys
+    // a long list is cut to the best E first; a short one (at most 128 exact, distinct keys)
+    // is ranked as it is
+    if (row.cnt > 128 && row.cnt > a.E) row.keep_best(a.E, true);
+    // emit in (distance, node id) order: the rank of each key among the list's keys; ranks
+    // from E on are not emitted
     const int n = row.cnt;
     const int64_t q = qidx[w];
-    for (int e = n + lane; e < a.E; e += 64) {
+    for (int e = min(n, a.E) + lane; e < a.E; e += 64) {
         a.out_ids[q * a.E + e] = -1;
         a.out_d[q * a.E + e] = __builtin_huge_valf();
     }
@@ -607,7 +781,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
         const uint64_t mine = i < n ? row.key[i] : ~0ull;
         int rank = 0;
         for (int j = 0; j < n; ++j) rank += row.key[j] < mine ? 1 : 0;
-        if (i < n) {
+        if (i < n && rank < a.E) {
             a.out_ids[q * a.E + rank] = static_cast<int32_t>(mine & 0xFFFFFFFFu);
             a.out_d[q * a.E + rank] = unord_f32(static_cast<uint32_t>(mine >> 32));
         }
@@ -677,15 +851,21 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     int dev = 0, max_lds = 64 * 1024;
     PA_HIP(hipGetDevice(&dev));
     PA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds = sizeof(float) * static_cast<size_t>(kTQ) * (d + kCH) +
+    const int ch = sl > 0 ? 2 * kCH : kCH;  // the kernel's chunk width
+    const size_t lds = sizeof(double) * static_cast<size_t>(kTQ) * d + sizeof(float) * static_cast<size_t>(kTQ) * (d + ch) +
                        static_cast<size_t>(kTQ) * cap * (sizeof(uint64_t) + (fp8 ? 0 : sizeof(float))) +
                        (fp8 ? static_cast<size_t>(kTQ) * d : 0);
     require(cap <= 16 * 64 && lds <= static_cast<size_t>(max_lds),
             "FES candidate list of a 16-query tile does not fit in LDS", PA_EUNSUPPORTED);
     hipLaunchKernelGGL(group_kernel, dim3(1), dim3(64 * kGroupWaves), 0, s, cluster, m, r, scratch_i32);
     PA_HIP(hipGetLastError());
-    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, cap, metric, scratch_i32, ids, dists};
-    const int blocks = static_cast<int>((m + kTQ - 1) / kTQ) + r;
+    // pivot rows (fp32, and FP8 codes) of all buckets beyond 4 MiB, the L2 of one XCD: group
+    // the tiles by XCD (the grid is then a multiple of 8; the extra blocks find no tile)
+    const int64_t table = static_cast<int64_t>(r) * n_b * d * (4 + (fp8 ? 1 : 0));
+    const int xcd = table > (int64_t(4) << 20) ? 1 : 0;
+    FesArgs a{Qr, d, EV, EV8, EVscale, EVnorm, EVid, r, n_b, E, K, cap, metric, xcd, scratch_i32, ids, dists};
+    int blocks = static_cast<int>((m + kTQ - 1) / kTQ) + r;
+    if (xcd) blocks = (blocks + 7) / 8 * 8;
     const int slots = cap / 64;
     auto go = [&](auto fp8_tag, auto s_tag, auto sl_tag) {
         constexpr bool F = decltype(fp8_tag)::value;
@@ -695,7 +875,7 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     };
     auto by_sl = [&](auto fp8_tag, auto s_tag) {
         using I = std::integral_constant<int, 0>;
-        if (decltype(fp8_tag)::value) {
+        if constexpr (decltype(fp8_tag)::value) {
             if (sl == 8) go(fp8_tag, s_tag, std::integral_constant<int, 8>{});
             else if (sl == 32) go(fp8_tag, s_tag, std::integral_constant<int, 32>{});
             else go(fp8_tag, s_tag, I{});

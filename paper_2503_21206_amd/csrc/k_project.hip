@@ -13,16 +13,17 @@ namespace {
 // y = x^T V_d for a block of 64 rows x 64 columns (256 threads, 4 x 4 outputs each).  The
 // method compares single-precision distances (section 6.1), and every later stage sees
 // only the reduced vectors, so the projection's fp32 output is defined as the exact
-// product rounded once: each output is a float-float (hi + lo) sum of exact products
-// (fma two-product, two-sum), renormalised after every K slice of 16, and rounded to fp32
-// at the end; fp16 / bf16 outputs are that fp32 value rounded to nearest even.  The result
-// is the correctly rounded value except when the exact sum lies within the pair's error
-// (about 2^-44 of sum |x_k v_k|) of a midpoint, and does not depend on the batch around a
-// row.  A plain fp32 MFMA product would differ from it in the last bits of most outputs,
-// and those bits move near-tied decisions of every stage after it.  The product is a
-// small part of a search (2 m D d_r flops against the traversal's gathers), so it runs on
-// the vector ALUs; the FES distance products stay on MFMA (their fp32 results only
-// pre-select candidates that are re-scored exactly).
+// product rounded once: each product x_k v_k of two fp32 values is exact in fp64, the
+// products are accumulated by fp64 fmas in order of k, and the sum is rounded to fp32 at
+// the end; fp16 / bf16 outputs are that fp32 value rounded to nearest even.  The sum is
+// within D 2^-53 of sum |x_k v_k| of the exact value, so the result is the correctly
+// rounded value except when the exact sum lies that close to a rounding boundary of fp32,
+// and it does not depend on the batch around a row.  A plain fp32 MFMA product would
+// differ from it in the last bits of most outputs, and those bits move near-tied
+// decisions of every stage after it.  The product is a small part of a search (2 m D d_r
+// flops against the traversal's gathers), so it runs on the vector ALUs (fp64 fma issues
+// at the fp32 rate on CDNA); the FES distance products stay on MFMA (their fp32 results
+// only pre-select candidates that are re-scored exactly).
 constexpr int kPM = 64;  // rows per block
 constexpr int kPN = 64;  // columns per block
 constexpr int kPK = 16;  // K slice staged in LDS
@@ -50,11 +51,11 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
     const int tc = t & 15;  // columns tc, tc+16, tc+32, tc+48 of the block
     const int64_t row0 = static_cast<int64_t>(blockIdx.x) * kPM;
     const int col0 = blockIdx.y * kPN;
-    ff32 acc[4][4];
+    double acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = ff32{0.0f, 0.0f};
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
 
     for (int k0 = 0; k0 < D; k0 += kPK) {
         {  // X: 64 rows x 16 k, four per thread
@@ -81,19 +82,15 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
 #pragma unroll 4
         for (int kk = 0; kk < kPK; ++kk) {
             const float4 xv = *reinterpret_cast<const float4*>(&Xs[kk][4 * tr]);
-            const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-            float vs[4];
+            const double xs[4] = {xv.x, xv.y, xv.z, xv.w};
+            double vs[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) vs[j] = Vs[kk][tc + 16 * j];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) ff_add_prod(acc[i][j], xs[i], vs[j]);
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fma(xs[i], vs[j], acc[i][j]);
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = ff_norm(acc[i][j]);
         __syncthreads();
     }
 #pragma unroll
@@ -104,7 +101,7 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
         for (int j = 0; j < 4; ++j) {
             const int col = col0 + tc + 16 * j;
             if (col >= d_r) continue;
-            const float v = acc[i][j].hi;  // normalised: hi is hi + lo rounded to fp32
+            const float v = static_cast<float>(acc[i][j]);  // rounded once, to nearest even
             const int64_t off = row * d_r + col;
             if (y_dtype == PA_F32) static_cast<float*>(Y)[off] = v;
             else if (y_dtype == PA_F16) static_cast<uint16_t*>(Y)[off] = f32_to_f16_bits(v);
@@ -114,47 +111,54 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------- routing
-// One wave per query: lane c < r scores centroid c with a float-float sum of squared
-// differences (the correctly rounded fp32 distance); the wave takes the minimum (ties to
-// the lowest c).
+// One wave per query.  Centroid c is scored by lanes c and c + 32 (r <= 32: each over one
+// half of the dimensions) or by lane c alone (r > 32): squared differences formed in fp64
+// and accumulated by fp64 fmas, the halves added (the same sum on both lanes), and the
+// result rounded once to fp32, which is the correctly rounded distance except within
+// (d_r + 2) 2^-53 (relative) of a rounding boundary of fp32.  The wave takes the minimum
+// (ties to the lowest c).
 __global__ __launch_bounds__(256) void route_kernel(const float* __restrict__ Qr, int64_t m, int d_r,
                                                     const float* __restrict__ C, int r,
                                                     int32_t* __restrict__ cluster) {
     const int lane = threadIdx.x & 63;
     const int64_t q = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (q >= m) return;
-    const float* qv = Qr + q * d_r;
-    float best = __builtin_huge_valf();
-    if (lane < r) {
-        // d_r is a multiple of 16: the rows are read as float4, 32 floats at a time, every
-        // load of a piece issued before its arithmetic
-        const float4* cv = reinterpret_cast<const float4*>(C + static_cast<int64_t>(lane) * d_r);
-        const float4* q4 = reinterpret_cast<const float4*>(qv);
-        ff32 s{0.0f, 0.0f};
-        for (int seg = 0; seg < d_r / 4; seg += 8) {
-            float4 c[8], x[8];
+    const bool halves = r <= 32;
+    const int c = halves ? (lane & 31) : lane;
+    const int len = halves ? d_r / 2 : d_r;  // d_r is a multiple of 16: both halves are float4 rows
+    const int off = (halves && lane >= 32) ? d_r / 2 : 0;
+    double s = 0.0;
+    if (c < r) {
+        const float4* cv = reinterpret_cast<const float4*>(C + static_cast<int64_t>(c) * d_r + off);
+        const float4* q4 = reinterpret_cast<const float4*>(Qr + q * d_r + off);
+        for (int seg = 0; seg < len / 4; seg += 4) {  // every load of a piece before its arithmetic
+            float4 cc[4], x[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool in = seg + u < d_r / 4;
-                c[u] = in ? cv[seg + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int u = 0; u < 4; ++u) {
+                const bool in = seg + u < len / 4;
+                cc[u] = in ? cv[seg + u] : make_float4(0.f, 0.f, 0.f, 0.f);
                 x[u] = in ? q4[seg + u] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                ff_add_sqdiff(s, x[u].x, c[u].x);
-                ff_add_sqdiff(s, x[u].y, c[u].y);
-                ff_add_sqdiff(s, x[u].z, c[u].z);
-                ff_add_sqdiff(s, x[u].w, c[u].w);
+            for (int u = 0; u < 4; ++u) {
+                const float xa[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+                const float ca[4] = {cc[u].x, cc[u].y, cc[u].z, cc[u].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double df = static_cast<double>(xa[e]) - static_cast<double>(ca[e]);
+                    s = __builtin_fma(df, df, s);
+                }
             }
         }
-        best = ff_norm(s).hi;  // the correctly rounded fp32 distance
     }
+    if (halves) s += __shfl_xor(s, 32);
+    const float best = static_cast<float>(s);
     // (distance, index) minimum across the wave, lowest index on ties
-    uint64_t key = (static_cast<uint64_t>(__float_as_uint(best)) << 32) | static_cast<uint32_t>(lane);
-    if (lane >= r) key = ~0ull;
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(key, off);
-        key = o < key ? o : key;
+    uint64_t key = (static_cast<uint64_t>(__float_as_uint(best)) << 32) | static_cast<uint32_t>(c);
+    if (c >= r) key = ~0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t v = __shfl_xor(key, o);
+        key = v < key ? v : key;
     }
     if (lane == 0) cluster[q] = static_cast<int32_t>(key & 0xFFFFFFFFu);
 }
