@@ -55,6 +55,7 @@ class WorkloadSpec:
     ef: tuple
     kind: str = "gmm"  # "gmm" (flat) | "hgmm" (nested) | "aniso"
     unit_norm: bool = True  # aniso only: every point scaled to unit length
+    centre_scale: float = 2.0  # aniso only: centres = centre_scale * B diag(sqrt(lambda)) z
     levels: tuple = ()
     spreads: tuple = ()
     r: int = 32
@@ -98,7 +99,7 @@ SPECS = {
         name="aniso100m", config=4, n=100_000_000, dim=96, components=16_384,
         queries=100_000, metric="l2", k=10, degree=32, d_r=48, rho=0.25,
         sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
-        kind="aniso", unit_norm=False, xr_dtypes=("f16",)),
+        kind="aniso", unit_norm=False, centre_scale=1.0, xr_dtypes=("f16",)),
     "serve20m": WorkloadSpec(
         name="serve20m", config=5, n=20_000_000, dim=768, components=1024,
         queries=100_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
@@ -137,13 +138,13 @@ def _basis(seed: int, dim: int) -> np.ndarray:
     return q * s[None, :]
 
 
-def _aniso_model(seed: int, components: int, dim: int):
+def _aniso_model(seed: int, components: int, dim: int, centre_scale: float = 2.0):
     b = _basis(seed, dim)
     lam = 1.0 / np.arange(1, dim + 1, dtype=np.float64)
     scale = b * np.sqrt(lam)[None, :]  # B diag(sqrt(lambda))
     rng = make_rng(seed, 0x7FFF_FFFE)
     z = rng.standard_normal((components, dim))
-    centres = 2.0 * z @ scale.T
+    centres = centre_scale * z @ scale.T
     return centres, scale
 
 
@@ -170,7 +171,7 @@ def _rows(spec: WorkloadSpec, stream_seed: int, total: int, start: int, stop: in
         if model.shape[0] != spec.components:
             raise ValueError("nested levels must multiply to the component count")
     else:
-        model = _aniso_model(spec.seed, spec.components, spec.dim)
+        model = _aniso_model(spec.seed, spec.components, spec.dim, spec.centre_scale)
     start, stop = max(0, start), min(total, stop)
     out = np.empty((max(0, stop - start), spec.dim), dtype=np.float32)
     c0, c1 = start // CHUNK, (stop - 1) // CHUNK if stop > start else -1
