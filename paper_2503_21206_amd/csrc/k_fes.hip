@@ -399,11 +399,10 @@ struct Row {
 
     // Re-scores every entry exactly (fp64 direct form, rounded once): four lanes per pivot,
     // lane s of the four taking the row's 16-byte pieces s, s + 4, s + 8, ... (a quad reads
-    // 64 contiguous bytes of the pivot per step, and the query's matching fp64 elements,
-    // 128 contiguous bytes of LDS, without bank conflicts); up to 4 pieces per lane and the
-    // node id are loaded before the arithmetic.  Sixteen pivots per pass.  qv: the query
-    // row in fp64.
-    __device__ void rescore(const double* qv, bool node_ids = false, int from = 0) {
+    // 64 contiguous bytes of the pivot per step, and the query's matching 64 bytes of LDS,
+    // without bank conflicts); up to 4 pieces per lane and the node id are loaded before
+    // the arithmetic.  Sixteen pivots per pass.  qv: the query row (fp32, in LDS).
+    __device__ void rescore(const float* qv, bool node_ids = false, int from = 0) {
         const int d = a.d, nq = d / 16, sub = lane & 3;  // pieces per lane (d % 16 == 0)
         constexpr int PW = 4;  // pieces loaded together
         for (int base = from; base < cnt; base += 16) {
@@ -422,9 +421,8 @@ struct Row {
 #pragma unroll
                 for (int u = 0; u < PW; ++u) {
                     if (s0 + u < nq) {
-                        const double2* q2 = reinterpret_cast<const double2*>(qv + 4 * (4 * (s0 + u) + sub));
-                        const double2 qa = q2[0], qb = q2[1];
-                        const double qd[4] = {qa.x, qa.y, qb.x, qb.y};
+                        const float4 qa = reinterpret_cast<const float4*>(qv)[4 * (s0 + u) + sub];
+                        const double qd[4] = {qa.x, qa.y, qa.z, qa.w};
                         const float xv[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
@@ -476,15 +474,15 @@ struct Row {
 // SL > 0: the row's n_b <= 64 SL scores stay in registers (SL per lane) and one selection
 // runs after the last chunk; SL == 0: the candidate list in LDS is shrunk as chunks arrive
 // (any bucket size).
-template <bool FP8, int S, int SL>
+template <bool FP8, int S, int SL, bool WIDE>
 __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // pivots per chunk: the register path takes 256 (one 16 x 16 block per wavefront, half
-    // as many block barriers), the list path 128 (its list keeps room for one chunk)
-    constexpr int CH = SL > 0 ? 2 * kCH : kCH;
+    // pivots per chunk: the register path takes 256 where LDS allows (one 16 x 16 block per
+    // wavefront, half as many block barriers), else 128 like the list path (whose list
+    // keeps room for one chunk)
+    constexpr int CH = (SL > 0 && WIDE) ? 2 * kCH : kCH;
     const int d = a.d;
-    double* Aq64 = reinterpret_cast<double*>(smem);                  // [kTQ][d] the rows in fp64
-    float* Aq = reinterpret_cast<float*>(Aq64 + kTQ * d);            // [kTQ][d]
+    float* Aq = reinterpret_cast<float*>(smem);                      // [kTQ][d]
     float* sc = Aq + kTQ * d;                                        // [kTQ][CH] chunk scores
     uint64_t* bkey = reinterpret_cast<uint64_t*>(sc + kTQ * CH);    // [kTQ][cap]
     float* beps = reinterpret_cast<float*>(bkey + kTQ * a.cap);      // [kTQ][cap] (FP32 form)
@@ -532,11 +530,6 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
         const float4 v = (i < cntq) ? reinterpret_cast<const float4*>(a.Qr + static_cast<int64_t>(qidx[i]) * d)[j]
                                     : make_float4(0.f, 0.f, 0.f, 0.f);
         reinterpret_cast<float4*>(Aq)[idx] = v;
-        double* q64 = Aq64 + 4 * idx;
-        q64[0] = v.x;
-        q64[1] = v.y;
-        q64[2] = v.z;
-        q64[3] = v.w;
     }
     __syncthreads();
     {  // the row's squared norm and FP8 scale (one wavefront per row)
@@ -657,7 +650,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                 if (!FP8 && row.cnt > a.cap - CH) {
                     // (the FP8 list keeps exactly K) more near ties around the
                     // threshold than the slack holds; decide them on exact distances now
-                    row.rescore(Aq64 + w * d);
+                    row.rescore(Aq + w * d);
                     const uint32_t worst = row.keep_best(a.E);
                     row.T32 = worst < row.T32 ? worst : row.T32;
                 }
@@ -733,7 +726,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                 }
             }
             wave_sync();
-            row.rescore(Aq64 + w * d, true);
+            row.rescore(Aq + w * d, true);
         } else {
             // drop the scores whose lower end exceeds the E-th smallest upper end
             const float qnw = qn[w];
@@ -750,7 +743,7 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                     const bool in = ok[i] && (!Row<FP8, S>::finite(sv[i]) || Row<FP8, S>::lo_ord(sv[i], se[i]) <= T);
                     const uint64_t m = __ballot(in);
                     if (row.cnt + __popcll(m) > a.cap) {  // near ties beyond the slack: decide a batch
-                        row.rescore(Aq64 + w * d, true, exact);
+                        row.rescore(Aq + w * d, true, exact);
                         row.keep_best(a.E, true);
                         exact = row.cnt;
                     }
@@ -759,11 +752,11 @@ __global__ __launch_bounds__(kThreads) void score_kernel(FesArgs a) {
                 }
             }
             wave_sync();
-            row.rescore(Aq64 + w * d, true, exact);
+            row.rescore(Aq + w * d, true, exact);
         }
     } else {
         row.shrink(want);
-        row.rescore(Aq64 + w * d, true);
+        row.rescore(Aq + w * d, true);
     }
     // a long list is cut to the best E first; a short one (at most 128 exact, distinct keys)
     // is ranked as it is
@@ -851,10 +844,15 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
     int dev = 0, max_lds = 64 * 1024;
     PA_HIP(hipGetDevice(&dev));
     PA_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int ch = sl > 0 ? 2 * kCH : kCH;  // the kernel's chunk width
-    const size_t lds = sizeof(double) * static_cast<size_t>(kTQ) * d + sizeof(float) * static_cast<size_t>(kTQ) * (d + ch) +
-                       static_cast<size_t>(kTQ) * cap * (sizeof(uint64_t) + (fp8 ? 0 : sizeof(float))) +
-                       (fp8 ? static_cast<size_t>(kTQ) * d : 0);
+    // the kernel's LDS for a chunk width: query rows, chunk scores, lists, FP8 query codes
+    auto lds_for = [&](int ch) {
+        return sizeof(float) * static_cast<size_t>(kTQ) * (d + ch) +
+               static_cast<size_t>(kTQ) * cap * (sizeof(uint64_t) + (fp8 ? 0 : sizeof(float))) +
+               (fp8 ? static_cast<size_t>(kTQ) * d : 0);
+    };
+    // the register path takes 256-pivot chunks where they fit
+    const bool wide = sl > 0 && lds_for(2 * kCH) <= static_cast<size_t>(max_lds);
+    const size_t lds = lds_for(wide ? 2 * kCH : kCH);
     require(cap <= 16 * 64 && lds <= static_cast<size_t>(max_lds),
             "FES candidate list of a 16-query tile does not fit in LDS", PA_EUNSUPPORTED);
     hipLaunchKernelGGL(group_kernel, dim3(1), dim3(64 * kGroupWaves), 0, s, cluster, m, r, scratch_i32);
@@ -871,7 +869,12 @@ void launch_select_entries_chunked(const float* Qr, const int32_t* cluster, int6
         constexpr bool F = decltype(fp8_tag)::value;
         constexpr int S_ = decltype(s_tag)::value;
         constexpr int SL_ = decltype(sl_tag)::value;
-        hipLaunchKernelGGL((score_kernel<F, S_, SL_>), dim3(blocks), dim3(kThreads), lds, s, a);
+        if constexpr (SL_ > 0) {
+            if (wide) hipLaunchKernelGGL((score_kernel<F, S_, SL_, true>), dim3(blocks), dim3(kThreads), lds, s, a);
+            else hipLaunchKernelGGL((score_kernel<F, S_, SL_, false>), dim3(blocks), dim3(kThreads), lds, s, a);
+        } else {
+            hipLaunchKernelGGL((score_kernel<F, S_, SL_, false>), dim3(blocks), dim3(kThreads), lds, s, a);
+        }
     };
     auto by_sl = [&](auto fp8_tag, auto s_tag) {
         using I = std::integral_constant<int, 0>;

@@ -513,6 +513,54 @@ def test_select_entries_fp8_preselect_then_fp32_rerank(dev, tiny, n_p, r):
     tally.done()
 
 
+
+def _ord_f32(v):
+    u = np.asarray(v, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return np.where(u & 0x80000000, (~u) & 0xFFFFFFFF, u | 0x80000000)
+
+
+@pytest.mark.parametrize("n_b,K,E,d", [(512, 64, 16, 32), (2048, 256, 256, 32), (2048, 256, 64, 32),
+                                       (4096, 256, 64, 32), (2048, 1024, 256, 128), (2048, 1024, 256, 256)])
+def test_fp8_preselection_exact_on_integer_data(dev, n_b, K, E, d):
+    # Small integers make every FP8 product sum exact in fp32 whatever the MFMA's order, so
+    # the K best by (FP8 score, position) are known exactly, ties included (integer data has
+    # many equal scores).  Buckets of 512 and 2,048 pivots keep the scores in registers
+    # (2,048: the narrowed K-th search), 4,096 the candidate list; E = K = 256 emits the whole
+    # pre-selection, re-scored exactly and ordered by (distance, node id).  K = 1,024 lists
+    # fill most of the LDS: at d = 128 with 256-pivot chunks, at d = 256 with 128-pivot chunks.
+    say(f"select_entries_fp8 on integer data: {n_b}-pivot buckets, d={d}, K={K}, E={E}")
+    rng = np.random.default_rng(n_b + K + E + d)
+    m, r = 300, 2
+    Q = rng.integers(-3, 4, (m, d)).astype(np.float32)
+    EV = rng.integers(-3, 4, (r, n_b, d)).astype(np.float32)
+    EVid = rng.permutation(r * n_b).astype(np.int32).reshape(r, n_b)
+    cl = rng.integers(0, r, m).astype(np.int32)
+    codes, scales = pa.quantize_fp8_rows(EV.reshape(-1, d))
+    ids, dist = pa.select_entries_fp8(_t(Q, dev), _t(cl, dev), _t(EV, dev), _t(codes.reshape(r, n_b, d), dev),
+                                      _t(scales.reshape(r, n_b), dev),
+                                      _t((EV.astype(np.float64) ** 2).sum(-1).astype(np.float32), dev), _t(EVid, dev),
+                                      E, K, "ip")
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    # expected: the query's e4m3 codes (scale max|q| / 448, round to nearest even), exact
+    # integer-multiple products, the score -acc * (s_q * s_p) in fp32
+    dec = lambda c: torch.from_numpy(np.ascontiguousarray(c)).view(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    p8 = dec(codes).reshape(r, n_b, d)
+    amax = np.abs(Q).max(1)
+    sq = np.where(amax > 0, amax / np.float32(448.0), np.float32(1.0)).astype(np.float32)
+    q8 = torch.from_numpy((Q / sq[:, None]).astype(np.float32)).to(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+    ps = scales.reshape(r, n_b)
+    for i in range(m):
+        c = cl[i]
+        acc = (p8[c] @ q8[i]).astype(np.float32)  # exact sums of exact products
+        score = -(acc * (sq[i] * ps[c]))
+        order = np.lexsort((np.arange(n_b), _ord_f32(score)))  # by (score, position)
+        pre = order[:K]
+        exact = (-(EV[c][pre].astype(np.float64) @ Q[i].astype(np.float64))).astype(np.float32)
+        key = (_ord_f32(exact) << np.uint64(32)) | EVid[c][pre].astype(np.uint64)
+        top = np.argsort(key, kind="stable")[:E]
+        assert (ids[i] == EVid[c][pre][top]).all(), i
+        assert (dist[i].view(np.uint32) == exact[top].view(np.uint32)).all(), i
+
 def test_index_with_fp8_pivots(dev, tiny):
     say("Index with fp8 pivots: search recall close to the fp32-pivot index")
     s = tiny["spec"]
