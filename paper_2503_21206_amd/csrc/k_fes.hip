@@ -14,7 +14,6 @@
 #include <type_traits>
 
 #include "common.hpp"
-#include "ffloat.hpp"
 
 namespace pa {
 namespace {

@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
-#include "ffloat.hpp"
 
 namespace pa {
 namespace {
