@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 << 20  # MI355X's last-level cache in front of HBM
 PROFILES = os.path.join(ROOT, "profiles")
 BEAM_SOURCES = ("k_beam.hip", "ffloat.hpp", "common.hpp")
 
@@ -467,7 +468,12 @@ def roofline(spec, agg, steps, ef, E, xr_bytes, form, visited=None):
     launches = agg["beam_launches"]
     avg_ms = agg["beam_ms"] / launches
     achieved = method / launches / (avg_ms / 1e3) / 1e9
+    # the traversal's tables: the sampled nodes' reduced rows and subgraph adjacency rows
+    n_sub = round(spec.rho * spec.n)
+    working_set = n_sub * (xr_bytes * spec.d_r + 4 * spec.degree)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "working_set_bytes": int(working_set),
+            "served_from": "infinity_cache" if working_set <= INFINITY_CACHE_BYTES else "hbm",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(spec.name, form, ef),
             "kernel": "beam_kernel", "bytes_per_launch": int(method / launches),
             "kernel_bytes_per_launch": int(kernel / launches),

@@ -323,9 +323,13 @@ def test_bench_roofline_counts_the_algorithmic_bytes():
     (list out) + 4*R per expansion (adjacency row) + s*d_r per distance (reduced row)."""
     import types
     import bench
-    spec = types.SimpleNamespace(name="hand", queries=10, d_r=64, degree=32)
+    spec = types.SimpleNamespace(name="hand", queries=10, d_r=64, degree=32, n=1_000_000, rho=0.25)
     agg = {"n_exp1": 650, "n_dist1": 8670, "beam_launches": 2, "beam_ms": 1.0}
     r = bench.roofline(spec, agg, 2, 64, 64, 4, "f32")
+    # the traversal's tables: 250,000 sampled rows of 256 + 128 bytes fit the 256 MB cache
+    assert r["working_set_bytes"] == 250_000 * 384 and r["served_from"] == "infinity_cache"
+    big = types.SimpleNamespace(name="hand", queries=10, d_r=48, degree=32, n=32_000_000, rho=0.25)
+    assert bench.roofline(big, agg, 2, 64, 64, 2, "f16")["served_from"] == "hbm"
     # 20 queries * (256 + 256 + 512) + 650 * 128 + 8670 * 256 = 20480 + 83200 + 2219520 bytes
     # over two launches of 0.5 ms each
     assert r["bytes_per_launch"] == (20480 + 83200 + 2219520) // 2
