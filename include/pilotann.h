@@ -319,7 +319,7 @@ typedef struct {
     int64_t hbm_budget;   /* bytes of HBM the index and search buffers may use (0 = no limit) */
     int32_t pivot_dtype;  /* PA_F32 or PA_FP8E4M3 (precision form of entry selection)   */
     int32_t preselect;    /* FP8 form: pivots re-scored in fp32 per query = preselect*E
-                             (0: 4), capped by the bucket size                         */
+                             (0: 4), capped by the bucket size and by 1,024 (at least E) */
     int32_t compact;      /* 1: HBM holds X_r and the subgraph for the sampled nodes
                              only (memory-bounded layout, section 4.3 drops the
                              unsampled nodes' vectors; see pa_index_build_subgraph);

@@ -65,7 +65,8 @@ void index_select_entries(const pa_index* idx, const float* Qr, const int32_t* c
     const int r = idx->p.r, d_r = idx->p.d_r;
     if (idx->p.pivot_dtype == PA_FP8E4M3) {
         const int mult = idx->p.preselect > 0 ? idx->p.preselect : 4;
-        const int K = std::min(std::max(E, mult * E), idx->n_b);
+        // at most 1,024 pre-selected pivots per query: a 16-query tile's lists fill the LDS
+        const int K = std::min(std::max(E, std::min(mult * E, 1024)), idx->n_b);
         launch_select_entries_chunked(Qr, cluster, m, d_r, static_cast<const float*>(idx->EV_dev.p),
                                       static_cast<const uint8_t*>(idx->EV8_dev.p),
                                       static_cast<const float*>(idx->EVs_dev.p),

@@ -87,7 +87,7 @@ SPECS = {
     "aniso10m": WorkloadSpec(
         name="aniso10m", config=3, n=10_000_000, dim=768, components=1024,
         queries=10_000, metric="ip", k=10, degree=48, d_r=128, rho=0.20,
-        sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256),
+        sample_mode="seed_expand", n_pivots=65_536, ef=(32, 48, 64, 96, 128, 192, 256, 384, 512),
         kind="aniso", xr_dtypes=("bf16",), pivot_dtype="fp8"),
     "gmm100m": WorkloadSpec(
         name="gmm100m", config=4, n=100_000_000, dim=96, components=16_384,

@@ -36,12 +36,15 @@ def _rank_exact(x64: torch.Tensor, q64: torch.Tensor, cand: torch.Tensor, metric
 
 @torch.no_grad()
 def exact_knn(X, Q, k: int, metric: str = "l2", *, device=None, exclude_self: bool = False,
-              margin: int = 16, budget_bytes: int | None = None, candidate_mask=None):
+              margin: int = 16, budget_bytes: int | None = None, candidate_mask=None,
+              fp64_scores: bool = False):
     """Exact top-k of each row of Q among rows of X.
 
     Returns (ids int64 [m][k], dists float64 [m][k]) as numpy arrays.  With
     ``exclude_self`` the query set is X itself and row i never returns i.
     ``candidate_mask`` (bool [n]) restricts the search to the marked rows.
+    ``fp64_scores`` takes the candidates from fp64 scores instead of an fp32 GEMM (for sets
+    whose nearest scores lie closer together than the fp32 products' rounding).
     """
     dev = pick_device(device)
     old_tf32 = torch.backends.cuda.matmul.allow_tf32
@@ -52,7 +55,8 @@ def exact_knn(X, Q, k: int, metric: str = "l2", *, device=None, exclude_self: bo
         n, m = xt.shape[0], qt.shape[0]
         kk = min(k + margin, n)
         x64 = xt.double()
-        xn = (x64 ** 2).sum(1).float()
+        xn64 = (x64 ** 2).sum(1)
+        xn = xn64.float()
         bias = None
         if candidate_mask is not None:
             cm = torch.as_tensor(np.asarray(candidate_mask, dtype=bool)).to(dev)
@@ -61,12 +65,16 @@ def exact_knn(X, Q, k: int, metric: str = "l2", *, device=None, exclude_self: bo
             budget_bytes = (6 << 30) if dev.type == "cuda" else (1 << 29)
         # a chunk's score matrix also stays below 2^30 elements (top-k over larger tensors
         # is not to be relied on)
-        bs = int(max(1, min(m, budget_bytes // max(1, 4 * n), (1 << 30) // max(1, n))))
+        width = 8 if fp64_scores else 4
+        bs = int(max(1, min(m, budget_bytes // max(1, width * n), (1 << 30) // max(1, n))))
         out_i = np.empty((m, min(k, n)), dtype=np.int64)
         out_d = np.empty((m, min(k, n)), dtype=np.float64)
         for q0 in range(0, m, bs):
             q = qt[q0:q0 + bs]
-            if metric == "l2":
+            if fp64_scores:
+                q64 = q.double()
+                s = (xn64[None, :] - 2.0 * (q64 @ x64.T)) if metric == "l2" else -(q64 @ x64.T)
+            elif metric == "l2":
                 s = xn[None, :] - 2.0 * (q @ xt.T)
             else:
                 s = -(q @ xt.T)
