@@ -134,7 +134,8 @@ __global__ __launch_bounds__(64 * kGroupWaves) void group_kernel(const int32_t* 
 // fmas; four lanes share a pivot and their partial sums are added pairwise, the same way on
 // every lane.  The fp64 sum is within (d + 4) 2^-53 of sum |term| of the exact value and is
 // rounded once to fp32: the correctly rounded distance unless the exact one lies within
-// that distance of a rounding boundary of fp32 (2^29 times closer than fp32's own spacing).
+// that distance of a rounding boundary of fp32 (at d = 128 about 2^23 times closer than
+// fp32's own spacing).
 // One fp64 fma per term replaces a float-float update of about 15 fp32 instructions, at
 // the same issue rate on CDNA.
 typedef long fp8x8 __attribute__((ext_vector_type(1)));
@@ -236,8 +237,9 @@ __device__ T kth_smallest(const T (&x)[S], const bool (&ok)[S], int slots, int k
     if (lo == hi) return lo;
     const int top = (BITS == 64) ? 63 - __clzll(static_cast<unsigned long long>(lo ^ hi))
                                  : 31 - __clz(static_cast<unsigned int>(lo ^ hi));
-    T v = lo & ~((T(2) << top) - 1);  // the common prefix (top < BITS - 1 here, or T(2) << top wraps to 0)
-    if (top == BITS - 1) v = 0;
+    // the bits above `top`, common to every valid value (none when top is the highest bit)
+    const T v0 = top == BITS - 1 ? T(0) : (lo & ~((T(2) << top) - 1));
+    T v = v0;
     for (int bit = top; bit >= 0; --bit) {
         const T probe = v | ((T(1) << bit) - 1);
         int c = 0;
