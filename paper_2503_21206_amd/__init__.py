@@ -147,6 +147,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2503_21206_amd.build`")
+        # PyTorch ships its own HIP runtime under the same soname: loaded first, it is the one
+        # this library binds to as well (loaded after this library, torch finds no GPU)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         h = C.CDLL(LIB_PATH)
         h.pa_last_error.restype = C.c_char_p
         h.pa_last_error.argtypes = []
