@@ -808,10 +808,14 @@ void launch_ch(const BeamArgs& a, hipStream_t s) {
 
 int beam_auto_cache_log2(int ef, int R) {
     // about 2.5 distance evaluations per expansion and ~ef expansions per query: size the
-    // cache so that it stays below half full (its reset threshold) for typical queries
+    // cache so that it stays below half full (its reset threshold) for typical queries.
+    // Lists of more than 256 entries take the smallest cache the kernel accepts instead:
+    // there the cache's LDS decides how many wavefronts share a CU, and more of them
+    // outweigh the re-scores after forgets (at ef 512 on 768-d rows: 2,048 slots 7.9 ms per
+    // 10,000 queries, 4,096 slots 12.3 ms, the same lists)
     (void)R;
     const int ef_alloc = (ef + 63) / 64 * 64;
-    int need = 6 * ef;
+    int need = ef > 256 ? 0 : 6 * ef;
     if (need < 4 * ef_alloc) need = 4 * ef_alloc;
     int lg = 10;
     while ((1 << lg) < need && lg < 13) ++lg;
